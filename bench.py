@@ -1,0 +1,192 @@
+"""Benchmark: a 34-qubit random grid circuit (2x17 lattice, depth 24, 1110
+gates) simulated on one MI355X through libsv.
+
+One step = |0..0> initialisation, fusion + every gate pass of the circuit
+(sv_apply_circuit), the FP64 norm reduction and a 2^20-amplitude read-back.
+The timed region holds exactly --steps steps between device synchronisations.
+
+Printed (one JSON line on stdout): gates/s of the configured path, the plain
+unfused FP32 path measured on the same GPU for comparison, the roofline of the
+dominant pass kernel (HIP events around every pass), and the CPU oracle timed
+on a bounded sample.  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "gates/s + HBM GB/s (34q c64); fused+MFMA vs plain FP32 at infidelity≤1e-6"
+HBM_PEAK_GBPS = 8000.0
+VARIANT_NAMES = {1: "k_apply_reg", 2: "k_apply_lds", 3: "k_apply_mfma"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name: str):
+    import circuits as C
+    if name == "grid34":
+        return 34, C.grid_circuit(2, 17, 24, seed=0), "34-qubit 2x17 random grid, depth 24, |0..0>"
+    if name == "grid30":
+        return 30, C.grid_circuit(5, 6, 20, seed=0), "30-qubit 5x6 random grid, depth 20, |0..0>"
+    if name == "grid20":
+        return 20, C.grid_circuit(4, 5, 14, seed=0), "20-qubit 4x5 random grid, depth 14, |0..0>"
+    raise SystemExit("unknown workload " + name)
+
+
+def run_step(st, gates, opts_kw, sample):
+    st.set_basis(0)
+    stats = st.apply_circuit(gates, stats=True, **opts_kw)
+    nrm = st.norm()
+    st.read(0, sample)
+    return stats, nrm
+
+
+def cpu_baseline(seconds_hint: float = 20.0) -> dict:
+    """The oracle (complex128, OpenMP, one gate at a time) on a 24-qubit 2x12
+    grid of the same depth and gate set; gates/s scaled to 34 qubits by the
+    state-size ratio 2^24 / 2^34 (the oracle's cost is linear in 2^n)."""
+    import circuits as C
+    import oracle
+    n = 24
+    gates = C.grid_circuit(2, 12, 24, seed=0)
+    oracle.build()
+    # time a prefix first and pick a sample that takes roughly seconds_hint
+    probe = gates[:40]
+    t0 = time.perf_counter()
+    oracle.apply_circuit(n, probe)
+    dt = time.perf_counter() - t0
+    per_gate = dt / len(probe)
+    count = max(40, min(len(gates), int(seconds_hint / max(per_gate, 1e-9))))
+    t0 = time.perf_counter()
+    oracle.apply_circuit(n, gates[:count])
+    dt = time.perf_counter() - t0
+    gps_24 = count / dt
+    return {
+        "value": gps_24 * 2.0 ** (24 - 34),
+        "unit": "gates/s",
+        "cores": oracle.threads(),
+        "kind": "oracle",
+        "sample": "first %d gates of a 24-qubit 2x12 grid circuit (depth 24) in %.1f s = %.3g gates/s at 24 "
+                  "qubits, scaled by 2^-10 to the 34-qubit state" % (count, dt, gps_24),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="grid34")
+    ap.add_argument("--max-k", type=int, default=4)
+    ap.add_argument("--fusion", default="greedy")
+    ap.add_argument("--precision", default="fp32_valu")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain unfused FP32 comparison run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2602_09604_amd import sv
+
+    n, gates, desc = workload(args.workload)
+    log("workload:", desc, "gates:", len(gates))
+    sample = 1 << 20
+    st = sv.State(n)
+    opts = dict(max_k=args.max_k, fusion=args.fusion, precision=args.precision, timing=True)
+
+    for i in range(args.warmup):
+        s, nrm = run_step(st, gates, opts, sample)
+        log("warmup %d: passes %d gpu %.3f s norm %.9f" % (i, s["passes"], s["gpu_s"], nrm))
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    agg = None
+    norms = []
+    for i in range(args.steps):
+        s, nrm = run_step(st, gates, opts, sample)
+        norms.append(nrm)
+        log("step %d: passes %d gpu %.3f s fuse %.3f s" % (i, s["passes"], s["gpu_s"], s["fuse_s"]))
+        if agg is None:
+            agg = s
+        else:
+            for key in ("gpu_s", "fuse_s", "useful_flops"):
+                agg[key] += s[key]
+            for v in range(4):
+                agg["variant_s"][v] += s["variant_s"][v]
+                agg["variant_passes"][v] += s["variant_passes"][v]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall / args.steps * 1e3
+    gates_per_s = len(gates) / (wall / args.steps)
+    passes = agg["variant_passes"]
+    dom = max(range(1, 4), key=lambda v: agg["variant_s"][v])
+    avg_launch = agg["variant_s"][dom] / max(1, passes[dom])
+    bytes_per_launch = 16.0 * (1 << n)
+    achieved = bytes_per_launch / avg_launch / 1e9
+    hbm_gbps_alg = agg["variant_passes"][1:4] and (sum(passes[1:4]) * bytes_per_launch / sum(agg["variant_s"][1:4]) / 1e9)
+
+    extra = {
+        "passes_per_step": int(sum(passes) / args.steps),
+        "fused_max_k": args.max_k, "fusion": args.fusion, "precision": args.precision,
+        "alg_hbm_GBps_passes": hbm_gbps_alg,
+        "gpu_s_per_step": agg["gpu_s"] / args.steps,
+        "fuse_s_per_step": agg["fuse_s"] / args.steps,
+        "norm_drift": max(abs(x - 1.0) for x in norms),
+        "per_variant": {VARIANT_NAMES[v]: {"passes": int(passes[v]), "avg_ms": 1e3 * agg["variant_s"][v] / passes[v]}
+                        for v in range(1, 4) if passes[v]},
+    }
+
+    if not args.no_plain:
+        log("plain unfused FP32 run ...")
+        st.set_basis(0)
+        p = st.apply_circuit(gates, fusion="none", precision="fp32_valu", stats=True, timing=True)
+        extra["plain_fp32_unfused"] = {
+            "gates_per_s": len(gates) / p["gpu_s"], "gpu_s": p["gpu_s"], "passes": p["passes"],
+            "alg_hbm_GBps": p["bytes"] / p["gpu_s"] / 1e9,
+        }
+        extra["speedup_vs_plain_fp32"] = gates_per_s / extra["plain_fp32_unfused"]["gates_per_s"]
+        log("plain: %.3f s" % p["gpu_s"])
+    st.free()
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(args.cpu_seconds)
+
+    line = {
+        "metric": METRIC,
+        "value": gates_per_s,
+        "unit": "gates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision in ("fp32_valu", "fp32_mfma") else args.precision,
+        "data": "synthetic",
+        "config": {"workload": desc, "qubits": n, "gates": len(gates), "state": "complex64",
+                   "fusion": args.fusion, "max_k": args.max_k, "precision": args.precision},
+        "roofline": {"bound": "hbm", "kernel": VARIANT_NAMES[dom], "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None},
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

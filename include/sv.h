@@ -1,0 +1,262 @@
+/*
+ * sv.h -- C ABI of libsv.so, a state-vector gate-application library for one
+ * AMD MI355X (gfx950) GPU.
+ *
+ * What it computes (Sec. II-A of the paper, Eq. 1-4): an n-qubit state is a
+ * vector of 2^n complex amplitudes; a k-qubit gate is a dense 2^k x 2^k
+ * complex matrix U applied by matrix-vector product to each of the 2^(n-k)
+ * groups of amplitudes that agree on every non-target bit and enumerate the
+ * target bits.  Gates on disjoint qubits combine by tensor product (Eq. 3) and
+ * gates on the same qubits by matrix product; the fusion pass (Sec. II-C,
+ * Sec. IV-D) builds such combined gates so that each pass over the state does
+ * more work per byte.
+ *
+ * Conventions used by every entry point:
+ *   - qubit q is bit q of the amplitude index (0-based, little-endian);
+ *   - a gate's matrix is row-major, 2^k x 2^k complex128 given as 2*4^k
+ *     doubles with re/im interleaved; local bit j of its row/column index is
+ *     state bit qubits[j]; the output is w = U v;
+ *   - the device state is complex64 with re/im interleaved (8 bytes per
+ *     amplitude), in a buffer the caller allocates and owns;
+ *   - every call returns an int status (SV_OK or a negative code); nothing
+ *     aborts or throws across the ABI; sv_last_error() describes the last
+ *     failure on the calling thread.  Validation happens before any device
+ *     work: a call that fails with SV_EINVAL leaves the state untouched.
+ *   - a HIP runtime failure returns SV_EDEVICE and poisons the handle: every
+ *     later call on it returns SV_ESTATE except sv_free.
+ *   - calls on one handle are not thread-safe; distinct handles are.
+ */
+#ifndef SV_H
+#define SV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define SV_OK 0
+#define SV_EINVAL (-1)        /* bad argument: qubit range/duplicate, k, null, sizes */
+#define SV_ENOMEM (-2)        /* buffer too small or an allocation failed */
+#define SV_EDEVICE (-3)       /* a HIP runtime call failed */
+#define SV_EUNSUPPORTED (-4)  /* valid request this build does not implement */
+#define SV_ESTATE (-5)        /* handle poisoned by an earlier device failure */
+
+/* ---- enumerations ------------------------------------------------------- */
+#define SV_C64 0              /* state dtype: complex64 (the only one built) */
+
+/* Arithmetic of a pass.  FP32_VALU: every pass on vector FP32 FMAs.
+ * FP32_MFMA: passes with k >= 4 as a real GEMM in the 4M form
+ * [Yr;Yi] = [[Ur,-Ui],[Ui,Ur]] [Xr;Xi] on FP32 matrix cores.
+ * BF16X3 / FP16X3: the same GEMM with every operand split into hi + lo
+ * halves of the narrow type and three products (hi*hi + hi*lo + lo*hi)
+ * accumulated in FP32; FP16X3 also scales each tile by a power of two. */
+#define SV_PREC_FP32_VALU 0
+#define SV_PREC_FP32_MFMA 1
+#define SV_PREC_BF16X3 2
+#define SV_PREC_FP16X3 3
+
+/* Fusion policy of sv_apply_circuit / sv_fuse.  NONE applies every gate as
+ * its own pass; GREEDY builds blocks of at most max_k qubits (vertical fusion
+ * by matrix product, horizontal by tensor product, per-qubit order kept);
+ * LEARNED scores candidate partitions with the cost-model network loaded by
+ * sv_cost_model_load and keeps the cheapest, falling back to GREEDY when no
+ * model is loaded. */
+#define SV_FUSE_NONE 0
+#define SV_FUSE_GREEDY 1
+#define SV_FUSE_LEARNED 2
+
+/* Kernel variant of a pass (for tests and tuning; AUTO is the default).
+ * REG: each lane owns whole groups in registers, gathered straight from HBM
+ * (coalesced when no target sits in the low 7 bits).  LDS: a workgroup
+ * stages a tile of 2^T amplitudes in LDS and scatters groups from there
+ * (for low targets).  MFMA: matrix-core GEMM (k >= 4 and an MFMA precision). */
+#define SV_VARIANT_AUTO 0
+#define SV_VARIANT_REG 1
+#define SV_VARIANT_LDS 2
+#define SV_VARIANT_MFMA 3
+
+#define SV_MAX_K 6            /* largest fused gate */
+#define SV_MAX_QUBITS 40      /* largest state the index arithmetic supports */
+#define SV_COST_FEATURES 40   /* k, n, 34-bit target mask, 4 precision one-hot */
+
+/* ---- types -------------------------------------------------------------- */
+typedef struct sv_state sv_state; /* opaque handle */
+
+/* One gate: k qubits (qubits[0..k-1], distinct, any order) and its matrix
+ * (2*4^k doubles, borrowed for the duration of the call only). */
+typedef struct {
+  int32_t k;
+  int32_t qubits[SV_MAX_K];
+  const double* matrix;
+} sv_gate;
+
+typedef struct {
+  int32_t max_k;      /* fusion block size limit, 1..6 (ignored for NONE) */
+  int32_t fusion;     /* SV_FUSE_* */
+  int32_t precision;  /* SV_PREC_* */
+  int32_t use_graph;  /* 1: launch the passes as one captured hipGraph */
+  int32_t variant;    /* SV_VARIANT_* (AUTO unless a test forces one) */
+  int32_t timing;     /* 1: bracket every pass with HIP events on the handle's
+                         stream and report per-variant device time in stats
+                         (needs stats; passes are then launched without a graph) */
+} sv_run_opts;
+
+typedef struct {
+  uint64_t gates_in;     /* gates given */
+  uint64_t passes;       /* fused passes launched */
+  uint64_t bytes;        /* algorithmic HBM bytes: passes * 16 * 2^n */
+  double useful_flops;   /* sum over passes of 2^(n-k) * 2^k (8*2^k - 2) */
+  double fuse_s;         /* host time in the fusion pass */
+  double gpu_s;          /* device time of the passes (HIP events) */
+  double variant_s[4];   /* with opts.timing: device time per SV_VARIANT_* (index 0 unused) */
+  uint64_t variant_passes[4]; /* with opts.timing: passes per SV_VARIANT_* */
+} sv_run_stats;
+
+/* ---- state -------------------------------------------------------------- */
+
+/* Wrap a caller-owned device buffer as an n-qubit complex64 state and write
+ * |0...0> into it (asynchronously on `hip_stream`, a hipStream_t or NULL for
+ * the default stream).  dev_buf must hold at least 8 * 2^n bytes and stay
+ * valid until sv_free; it is never freed by the library.  1 <= n <= 40.
+ * The library allocates only the handle and a small device arena for gate
+ * matrices and reduction partials.  Errors: SV_EINVAL (n, dtype, null),
+ * SV_ENOMEM (buf_bytes < 8 * 2^n or arena allocation). */
+int sv_alloc(int n_qubits, int dtype, void* dev_buf, size_t buf_bytes, void* hip_stream,
+             sv_state** out);
+
+/* Release the handle and its arena (waits for the handle's stream first).
+ * Never frees the borrowed state buffer.  NULL is accepted. */
+int sv_free(sv_state* s);
+
+/* Overwrite the state with the basis state |index> (asynchronous).
+ * SV_EINVAL if index >= 2^n. */
+int sv_set_basis(sv_state* s, uint64_t index);
+
+/* Number of qubits of a handle (or SV_EINVAL for NULL). */
+int sv_num_qubits(const sv_state* s);
+
+/* ---- gate application (Eq. 4) ------------------------------------------- */
+
+/* Apply one k-qubit gate (1 <= k <= min(6, n)) in FP32 on the handle's
+ * stream.  The matrix is rounded once to complex64 and copied before the
+ * call returns, so the caller may reuse it immediately.  Asynchronous.
+ * SV_EINVAL: qubit out of range or repeated, bad k, NULL matrix/qubits. */
+int sv_apply_gate(sv_state* s, const int32_t* qubits, int k, const double* matrix);
+
+/* Apply a circuit: validate all gates, fuse them per opts (FP64 on the host),
+ * round each fused matrix once to the pass precision, upload every matrix
+ * with one host-to-device copy, then launch one in-place pass per fused gate
+ * (as one hipGraph when opts->use_graph).  opts NULL means {max_k 4, GREEDY,
+ * FP32_VALU, no graph, AUTO}.  FUSE_NONE + FP32_VALU is the plain unfused
+ * FP32 baseline: same kernels, one pass per gate.  When stats is not NULL the
+ * call waits for the passes and fills it; otherwise it returns once the work
+ * is queued.  The result equals applying the gates one at a time in order,
+ * up to FP32 (or split-precision) rounding. */
+int sv_apply_circuit(sv_state* s, const sv_gate* gates, size_t n_gates, const sv_run_opts* opts,
+                     sv_run_stats* stats);
+
+/* ---- fusion (Sec. II-C, Sec. IV-D; Eq. 3) ------------------------------- */
+
+/* Fuse a gate list on the host in FP64 without touching any device.  On
+ * success *out is a library-allocated array of *n_out fused gates whose
+ * qubits are ascending and whose matrices are the ordered products of the
+ * absorbed gates lifted to the block's qubits; (*block_of_gate)[i] is the
+ * index of the fused gate that absorbed input gate i.  Applying *out in order
+ * equals applying `in` in order.  Free with sv_fused_free.  n_qubits bounds
+ * the qubit indices.  block_of_gate may be NULL. */
+int sv_fuse(const sv_gate* in, size_t n_in, int n_qubits, const sv_run_opts* opts, sv_gate** out,
+            size_t* n_out, int32_t** block_of_gate);
+int sv_fused_free(sv_gate* fused, size_t n, int32_t* block_of_gate);
+
+/* ---- reductions and read-back ------------------------------------------- */
+
+/* sum_i |c_i|^2 (Eq. 1), FP32 products accumulated in FP64 through a
+ * two-level block reduction.  Synchronises the handle's stream. */
+int sv_norm(sv_state* s, double* norm_sq);
+
+/* Copy amplitudes [start, start + count) to host memory as complex64
+ * (2*count floats, re/im interleaved), in chunks of 2^26 amplitudes.
+ * Synchronous.  SV_EINVAL if start + count > 2^n or host_out is NULL. */
+int sv_read_amplitudes(sv_state* s, uint64_t start, uint64_t count, float* host_out);
+
+/* Copy amplitudes from host (complex64, interleaved) into [start, start+count).
+ * Synchronous.  Used to load a prepared state or a checkpoint. */
+int sv_write_amplitudes(sv_state* s, uint64_t start, uint64_t count, const float* host_in);
+
+/* ---- batching ------------------------------------------------------------ */
+
+/* Run n_circuits independent circuits, circuit c on states[c] (each handle on
+ * the same device; the stream of states[0] is used), as one launch of the
+ * batched persistent kernel captured in a hipGraph.  Circuits whose state
+ * fits in LDS (n <= 14) are simulated entirely on chip; larger ones are
+ * swept through HBM by the same kernel with a per-circuit barrier between
+ * fused gates.  Gates are fused per opts->max_k (GREEDY) first.  When stats
+ * is not NULL the call waits and fills it.  Equivalent to sv_apply_circuit on
+ * each state in turn. */
+int sv_batch_run(sv_state* const* states, const sv_gate* const* circuits, const size_t* n_gates,
+                 size_t n_circuits, const sv_run_opts* opts, sv_run_stats* stats);
+
+/* ---- autotuner ----------------------------------------------------------- */
+
+/* Time the candidate tile shapes of every kernel variant on a scratch state
+ * of n qubits on the handle's device (the handle's state is overwritten) and
+ * keep the fastest per (variant, k, lowest-target bucket, precision).
+ * Results persist across calls in this process; sv_tune_save/sv_tune_load
+ * write and read them as JSON. */
+int sv_autotune(sv_state* s, int budget_ms);
+int sv_tune_save(const char* path);
+int sv_tune_load(const char* path);
+
+/* ---- learned fusion cost model (3-layer MLP, FP32, trained on the GPU) --- */
+
+typedef struct sv_mlp sv_mlp; /* opaque: parameters + Adam moments on the device */
+
+/* Network SV_COST_FEATURES -> width -> width -> 1 with ReLU; parameters drawn
+ * He-uniform from a SplitMix64 stream seeded by `seed`.  All device work on
+ * hip_stream. */
+int sv_mlp_create(int width, uint64_t seed, void* hip_stream, sv_mlp** out);
+int sv_mlp_free(sv_mlp* m);
+/* Number of parameters and their flat layout: W1 [width x F], b1 [width],
+ * W2 [width x width], b2 [width], W3 [1 x width], b3 [1] (row-major). */
+int sv_mlp_num_params(const sv_mlp* m, size_t* count);
+int sv_mlp_get_params(sv_mlp* m, float* host_params);
+int sv_mlp_set_params(sv_mlp* m, const float* host_params);
+/* Forward pass on device arrays: x [batch x SV_COST_FEATURES] -> y [batch]. */
+int sv_mlp_forward(sv_mlp* m, const float* x_dev, int batch, float* y_dev);
+/* Mean squared error of forward(x) against y and its gradient with respect to
+ * every parameter (same layout as the parameters), both copied to the host;
+ * grad_host may be NULL. */
+int sv_mlp_loss_grad(sv_mlp* m, const float* x_dev, const float* y_dev, int batch, float* loss_host,
+                     float* grad_host);
+/* One Adam update with the gradient of the last sv_mlp_loss_grad. */
+int sv_mlp_adam_step(sv_mlp* m, float lr, float beta1, float beta2, float eps);
+/* Full-batch training loop on the device (loss_grad + adam per epoch);
+ * *final_loss receives the last loss. */
+int sv_mlp_train(sv_mlp* m, const float* x_dev, const float* y_dev, int n, int epochs, float lr,
+                 float* final_loss);
+/* Install the network's current parameters as the cost model used by
+ * SV_FUSE_LEARNED (host copy; the network may be freed afterwards), or load
+ * / save them from / to a little-endian float32 file with a small header. */
+int sv_cost_model_install(sv_mlp* m);
+int sv_cost_model_save(const char* path);
+int sv_cost_model_load(const char* path);
+/* Host-side prediction of log(pass seconds / 2^n) for a gate (k, qubits,
+ * n, precision) under the installed model: what the partition search uses. */
+int sv_cost_model_predict(int k, const int32_t* qubits, int n_qubits, int precision, double* out);
+/* Feature vector of a pass as the model sees it (SV_COST_FEATURES floats). */
+int sv_cost_features(int k, const int32_t* qubits, int n_qubits, int precision, float* out);
+
+/* ---- diagnostics --------------------------------------------------------- */
+
+/* Describe the last failure on this thread; valid until the next call. */
+const char* sv_last_error(void);
+/* Library version string. */
+const char* sv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SV_H */

@@ -1,0 +1,466 @@
+// C ABI of libsv.so: state handles, gate application, fusion entry points,
+// norm and read-back.  All device work goes to the handle's stream.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "sv_internal.h"
+
+struct sv_state {
+  int n = 0;
+  void* psi = nullptr;          // borrowed complex64 buffer
+  hipStream_t stream = nullptr;
+  int device = 0;
+  bool poisoned = false;
+  // matrix arena: pinned host staging + device copy, used as a ring
+  unsigned char* arena_dev = nullptr;
+  unsigned char* arena_host = nullptr;
+  size_t arena_cap = 0;
+  size_t ring_pos = 0;
+  // reductions
+  double* partials = nullptr;
+  double* norm_dev = nullptr;
+  double* norm_host = nullptr;  // pinned
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<hipEvent_t> pass_events;  // per-pass timing events (grown on demand)
+};
+
+namespace sv {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+static constexpr size_t kArenaInit = (size_t)4 << 20;
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static void arena_reserve(sv_state* s, size_t bytes) {
+  if (bytes <= s->arena_cap) return;
+  SV_HIP(hipStreamSynchronize(s->stream));
+  if (s->arena_dev) SV_HIP(hipFree(s->arena_dev));
+  if (s->arena_host) SV_HIP(hipHostFree(s->arena_host));
+  s->arena_dev = nullptr;
+  s->arena_host = nullptr;
+  s->arena_cap = 0;
+  size_t cap = kArenaInit;
+  while (cap < bytes) cap *= 2;
+  SV_HIP(hipMalloc(&s->arena_dev, cap));
+  SV_HIP(hipHostMalloc(&s->arena_host, cap, hipHostMallocDefault));
+  s->arena_cap = cap;
+  s->ring_pos = 0;
+}
+
+// Reserve `bytes` of the ring; waits for the stream when the ring wraps so
+// that pinned staging bytes still being copied are never overwritten.
+static size_t arena_take(sv_state* s, size_t bytes) {
+  bytes = align256(bytes);
+  if (bytes > s->arena_cap) arena_reserve(s, bytes);
+  if (s->ring_pos + bytes > s->arena_cap) {
+    SV_HIP(hipStreamSynchronize(s->stream));
+    s->ring_pos = 0;
+  }
+  const size_t off = s->ring_pos;
+  s->ring_pos += bytes;
+  return off;
+}
+
+static void drop_graph(sv_state* s) {
+  if (s->graph_exec) {
+    SV_HIP(hipStreamSynchronize(s->stream));
+    SV_HIP(hipGraphExecDestroy(s->graph_exec));
+    s->graph_exec = nullptr;
+  }
+}
+
+static double useful_flops(int n, int k) {
+  return std::ldexp(1.0, n - k) * (double)(1 << k) * (8.0 * (1 << k) - 2.0);
+}
+
+// Resolve variants, encode all pass data into one staging region, copy it
+// with one host-to-device transfer, and launch the passes (optionally as one
+// captured graph).
+static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const sv_run_opts& o,
+                       sv_run_stats* stats) {
+  std::vector<Pass> passes(fused.size());
+  size_t total = 0;
+  for (size_t i = 0; i < fused.size(); ++i) {
+    Pass& p = passes[i];
+    p.k = fused[i].k;
+    std::copy(fused[i].q, fused[i].q + p.k, p.s);
+    p.precision = o.precision;
+    p.variant = choose_variant(s->n, p.k, p.s, o.precision, o.variant);
+    const Shape sh = tuned_shape(p.variant, s->n, p.k, p.s, o.precision);
+    p.tile_bits = sh.tile_bits;
+    p.reg_iters = sh.reg_iters;
+    p.mfma_cols = sh.mfma_cols;
+    p.mat_bytes = pass_data_bytes(p);
+    p.mat_off = total;
+    total += align256(p.mat_bytes);
+  }
+  if (total == 0) return;
+  drop_graph(s);
+  const size_t base = arena_take(s, total);
+  for (size_t i = 0; i < passes.size(); ++i) {
+    passes[i].mat_off += base;
+    encode_pass_data(passes[i], fused[i].mat.data(), s->arena_host + passes[i].mat_off);
+  }
+  SV_HIP(hipMemcpyAsync(s->arena_dev + base, s->arena_host + base, total, hipMemcpyHostToDevice, s->stream));
+  if (stats) SV_HIP(hipEventRecord(s->ev0, s->stream));
+  const bool timing = o.timing && stats;
+  const bool graph = o.use_graph && s->stream != nullptr && !timing;
+  if (timing) {
+    while (s->pass_events.size() < passes.size() + 1) {
+      hipEvent_t e;
+      SV_HIP(hipEventCreate(&e));
+      s->pass_events.push_back(e);
+    }
+    SV_HIP(hipEventRecord(s->pass_events[0], s->stream));
+    for (size_t i = 0; i < passes.size(); ++i) {
+      launch_pass(passes[i], s->n, s->psi, s->arena_dev, s->stream);
+      SV_HIP(hipEventRecord(s->pass_events[i + 1], s->stream));
+    }
+  } else if (graph) {
+    SV_HIP(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    try {
+      for (const Pass& p : passes) launch_pass(p, s->n, s->psi, s->arena_dev, s->stream);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(s->stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    hipGraph_t g = nullptr;
+    SV_HIP(hipStreamEndCapture(s->stream, &g));
+    hipError_t e = hipGraphInstantiate(&s->graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) throw DeviceError{e, "hipGraphInstantiate"};
+    SV_HIP(hipGraphLaunch(s->graph_exec, s->stream));
+  } else {
+    for (const Pass& p : passes) launch_pass(p, s->n, s->psi, s->arena_dev, s->stream);
+  }
+  if (stats) {
+    SV_HIP(hipEventRecord(s->ev1, s->stream));
+    SV_HIP(hipEventSynchronize(s->ev1));
+    float ms = 0.f;
+    SV_HIP(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+    stats->gpu_s = ms * 1e-3;
+    stats->passes = passes.size();
+    stats->bytes = (uint64_t)passes.size() * ((uint64_t)16 << s->n);
+    double fl = 0.0;
+    for (const Pass& p : passes) fl += useful_flops(s->n, p.k);
+    stats->useful_flops = fl;
+    if (timing) {
+      for (size_t i = 0; i < passes.size(); ++i) {
+        float pm = 0.f;
+        SV_HIP(hipEventElapsedTime(&pm, s->pass_events[i], s->pass_events[i + 1]));
+        const int v = passes[i].variant;
+        stats->variant_s[v] += pm * 1e-3;
+        stats->variant_passes[v] += 1;
+      }
+    }
+  }
+}
+
+static sv_run_opts default_opts() {
+  sv_run_opts o{};
+  o.max_k = 4;
+  o.fusion = SV_FUSE_GREEDY;
+  o.precision = SV_PREC_FP32_VALU;
+  o.use_graph = 0;
+  o.variant = SV_VARIANT_AUTO;
+  return o;
+}
+
+static int check_opts(const sv_run_opts& o) {
+  if (o.fusion < SV_FUSE_NONE || o.fusion > SV_FUSE_LEARNED) return fail(SV_EINVAL, "opts.fusion invalid");
+  if (o.fusion != SV_FUSE_NONE && (o.max_k < 1 || o.max_k > SV_MAX_K))
+    return fail(SV_EINVAL, "opts.max_k must be 1..6");
+  if (o.precision < SV_PREC_FP32_VALU || o.precision > SV_PREC_FP16X3)
+    return fail(SV_EINVAL, "opts.precision invalid");
+  if (o.variant < SV_VARIANT_AUTO || o.variant > SV_VARIANT_MFMA) return fail(SV_EINVAL, "opts.variant invalid");
+  if (o.timing != 0 && o.timing != 1) return fail(SV_EINVAL, "opts.timing must be 0 or 1");
+  return SV_OK;
+}
+
+// Fuse per opts into `fused`.
+int plan_fusion(const sv_gate* g, size_t n, int n_qubits, const sv_run_opts& o, std::vector<FusedGate>& fused,
+                std::vector<int32_t>& block_of) {
+  if (o.fusion == SV_FUSE_NONE) {
+    fuse_none(g, n, fused, block_of);
+  } else if (o.fusion == SV_FUSE_LEARNED) {
+    if (!fuse_learned(g, n, n_qubits, o.max_k, o.precision, fused, block_of))
+      fuse_greedy(g, n, o.max_k, fused, block_of);
+  } else {
+    fuse_greedy(g, n, o.max_k, fused, block_of);
+  }
+  return SV_OK;
+}
+
+}  // namespace sv
+
+using namespace sv;
+
+#define SV_GUARD_BEGIN try {
+#define SV_GUARD_END(handle)                                                                  \
+  }                                                                                           \
+  catch (const DeviceError& e) {                                                              \
+    if (handle) (handle)->poisoned = true;                                                    \
+    return fail(SV_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.err));           \
+  }                                                                                           \
+  catch (const std::bad_alloc&) {                                                             \
+    return fail(SV_ENOMEM, "host allocation failed");                                         \
+  }                                                                                           \
+  catch (const std::exception& e) {                                                           \
+    return fail(SV_EINVAL, e.what());                                                         \
+  }                                                                                           \
+  catch (...) {                                                                               \
+    return fail(SV_EINVAL, "unknown failure");                                                \
+  }
+
+static int check_handle(sv_state* s) {
+  if (!s) return fail(SV_EINVAL, "state handle is NULL");
+  if (s->poisoned) return fail(SV_ESTATE, "handle poisoned by an earlier device failure");
+  return SV_OK;
+}
+
+extern "C" {
+
+const char* sv_last_error(void) { return g_last_error.c_str(); }
+const char* sv_version(void) { return "libsv 0.1.0 (gfx950)"; }
+
+int sv_alloc(int n_qubits, int dtype, void* dev_buf, size_t buf_bytes, void* hip_stream, sv_state** out) {
+  if (!out) return fail(SV_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (dtype != SV_C64) return fail(SV_EINVAL, "only SV_C64 states are supported");
+  if (n_qubits < 1 || n_qubits > SV_MAX_QUBITS) return fail(SV_EINVAL, "n_qubits must be 1..40");
+  if (!dev_buf) return fail(SV_EINVAL, "dev_buf is NULL");
+  const size_t need = (size_t)8 << n_qubits;
+  if (buf_bytes < need) return fail(SV_ENOMEM, "buffer holds " + std::to_string(buf_bytes) + " bytes, need " +
+                                                   std::to_string(need));
+  if (((uintptr_t)dev_buf & 15) != 0) return fail(SV_EINVAL, "dev_buf must be 16-byte aligned");
+  sv_state* s = nullptr;
+  SV_GUARD_BEGIN
+  s = new sv_state();
+  s->n = n_qubits;
+  s->psi = dev_buf;
+  s->stream = (hipStream_t)hip_stream;
+  SV_HIP(hipGetDevice(&s->device));
+  SV_HIP(hipMalloc(&s->partials, sizeof(double) * (norm_partials_needed() + 1)));
+  s->norm_dev = s->partials + norm_partials_needed();
+  SV_HIP(hipHostMalloc(&s->norm_host, sizeof(double), hipHostMallocDefault));
+  SV_HIP(hipEventCreate(&s->ev0));
+  SV_HIP(hipEventCreate(&s->ev1));
+  arena_reserve(s, kArenaInit);
+  launch_init_basis(s->psi, s->n, 0, s->stream);
+  *out = s;
+  return SV_OK;
+  }
+  catch (const DeviceError& e) {
+    sv_free(s);
+    return fail(e.err == hipErrorOutOfMemory ? SV_ENOMEM : SV_EDEVICE,
+                std::string(e.what) + ": " + hipGetErrorString(e.err));
+  }
+  catch (const std::bad_alloc&) {
+    sv_free(s);
+    return fail(SV_ENOMEM, "host allocation failed");
+  }
+}
+
+int sv_free(sv_state* s) {
+  if (!s) return SV_OK;
+  (void)hipSetDevice(s->device);
+  (void)hipStreamSynchronize(s->stream);
+  if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+  if (s->arena_dev) (void)hipFree(s->arena_dev);
+  if (s->arena_host) (void)hipHostFree(s->arena_host);
+  if (s->partials) (void)hipFree(s->partials);
+  if (s->norm_host) (void)hipHostFree(s->norm_host);
+  if (s->ev0) (void)hipEventDestroy(s->ev0);
+  if (s->ev1) (void)hipEventDestroy(s->ev1);
+  for (hipEvent_t e : s->pass_events) (void)hipEventDestroy(e);
+  delete s;
+  return SV_OK;
+}
+
+int sv_num_qubits(const sv_state* s) { return s ? s->n : fail(SV_EINVAL, "state handle is NULL"); }
+
+int sv_set_basis(sv_state* s, uint64_t index) {
+  if (int rc = check_handle(s)) return rc;
+  if (index >> s->n) return fail(SV_EINVAL, "basis index out of range");
+  SV_GUARD_BEGIN
+  SV_HIP(hipSetDevice(s->device));
+  launch_init_basis(s->psi, s->n, index, s->stream);
+  return SV_OK;
+  SV_GUARD_END(s)
+}
+
+int sv_apply_gate(sv_state* s, const int32_t* qubits, int k, const double* matrix) {
+  if (int rc = check_handle(s)) return rc;
+  if (!qubits) return fail(SV_EINVAL, "qubits is NULL");
+  if (k < 1 || k > SV_MAX_K) return fail(SV_EINVAL, "k must be 1..6");
+  sv_gate g{};
+  g.k = k;
+  std::copy(qubits, qubits + k, g.qubits);
+  g.matrix = matrix;
+  if (int rc = validate_gates(&g, 1, s->n)) return rc;
+  SV_GUARD_BEGIN
+  SV_HIP(hipSetDevice(s->device));
+  std::vector<FusedGate> fused;
+  std::vector<int32_t> block_of;
+  fuse_none(&g, 1, fused, block_of);
+  sv_run_opts o = default_opts();
+  o.fusion = SV_FUSE_NONE;
+  run_passes(s, fused, o, nullptr);
+  return SV_OK;
+  SV_GUARD_END(s)
+}
+
+int sv_apply_circuit(sv_state* s, const sv_gate* gates, size_t n_gates, const sv_run_opts* opts,
+                     sv_run_stats* stats) {
+  if (int rc = check_handle(s)) return rc;
+  const sv_run_opts o = opts ? *opts : default_opts();
+  if (int rc = check_opts(o)) return rc;
+  if (int rc = validate_gates(gates, n_gates, s->n)) return rc;
+  SV_GUARD_BEGIN
+  SV_HIP(hipSetDevice(s->device));
+  if (stats) *stats = sv_run_stats{};
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<FusedGate> fused;
+  std::vector<int32_t> block_of;
+  plan_fusion(gates, n_gates, s->n, o, fused, block_of);
+  const double fuse_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  run_passes(s, fused, o, stats);
+  if (stats) {
+    stats->gates_in = n_gates;
+    stats->fuse_s = fuse_s;
+  }
+  return SV_OK;
+  SV_GUARD_END(s)
+}
+
+int sv_fuse(const sv_gate* in, size_t n_in, int n_qubits, const sv_run_opts* opts, sv_gate** out, size_t* n_out,
+            int32_t** block_of_gate) {
+  if (!out || !n_out) return fail(SV_EINVAL, "out / n_out is NULL");
+  *out = nullptr;
+  *n_out = 0;
+  if (block_of_gate) *block_of_gate = nullptr;
+  if (n_qubits < 1 || n_qubits > SV_MAX_QUBITS) return fail(SV_EINVAL, "n_qubits must be 1..40");
+  const sv_run_opts o = opts ? *opts : default_opts();
+  if (int rc = check_opts(o)) return rc;
+  if (int rc = validate_gates(in, n_in, n_qubits)) return rc;
+  try {
+    std::vector<FusedGate> fused;
+    std::vector<int32_t> block_of;
+    plan_fusion(in, n_in, n_qubits, o, fused, block_of);
+    // one allocation for the gate array, a second for all matrices
+    size_t doubles = 0;
+    for (auto& f : fused) doubles += f.mat.size();
+    sv_gate* g = (sv_gate*)std::malloc(sizeof(sv_gate) * (fused.size() ? fused.size() : 1));
+    double* m = (double*)std::malloc(sizeof(double) * (doubles ? doubles : 1));
+    if (!g || !m) {
+      std::free(g);
+      std::free(m);
+      return fail(SV_ENOMEM, "host allocation failed");
+    }
+    size_t pos = 0;
+    for (size_t i = 0; i < fused.size(); ++i) {
+      g[i] = sv_gate{};
+      g[i].k = fused[i].k;
+      std::copy(fused[i].q, fused[i].q + fused[i].k, g[i].qubits);
+      std::memcpy(m + pos, fused[i].mat.data(), sizeof(double) * fused[i].mat.size());
+      g[i].matrix = m + pos;
+      pos += fused[i].mat.size();
+    }
+    if (fused.empty()) std::free(m);
+    if (block_of_gate) {
+      int32_t* b = (int32_t*)std::malloc(sizeof(int32_t) * (n_in ? n_in : 1));
+      if (!b) {
+        std::free(g);
+        if (!fused.empty()) std::free(m);
+        return fail(SV_ENOMEM, "host allocation failed");
+      }
+      std::copy(block_of.begin(), block_of.end(), b);
+      *block_of_gate = b;
+    }
+    *out = g;
+    *n_out = fused.size();
+    return SV_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(SV_ENOMEM, "host allocation failed");
+  }
+}
+
+int sv_fused_free(sv_gate* fused, size_t n, int32_t* block_of_gate) {
+  if (fused && n > 0) std::free((void*)fused[0].matrix);
+  std::free(fused);
+  std::free(block_of_gate);
+  return SV_OK;
+}
+
+int sv_norm(sv_state* s, double* norm_sq) {
+  if (int rc = check_handle(s)) return rc;
+  if (!norm_sq) return fail(SV_EINVAL, "norm_sq is NULL");
+  SV_GUARD_BEGIN
+  SV_HIP(hipSetDevice(s->device));
+  launch_norm(s->psi, s->n, s->partials, norm_partials_needed(), s->norm_dev, s->stream);
+  SV_HIP(hipMemcpyAsync(s->norm_host, s->norm_dev, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  SV_HIP(hipStreamSynchronize(s->stream));
+  *norm_sq = *s->norm_host;
+  return SV_OK;
+  SV_GUARD_END(s)
+}
+
+int sv_read_amplitudes(sv_state* s, uint64_t start, uint64_t count, float* host_out) {
+  if (int rc = check_handle(s)) return rc;
+  if (!host_out && count) return fail(SV_EINVAL, "host_out is NULL");
+  const uint64_t len = (uint64_t)1 << s->n;
+  if (start > len || count > len - start) return fail(SV_EINVAL, "amplitude range out of bounds");
+  SV_GUARD_BEGIN
+  SV_HIP(hipSetDevice(s->device));
+  const uint64_t chunk = (uint64_t)1 << 26;
+  for (uint64_t done = 0; done < count; done += chunk) {
+    const uint64_t c = std::min(chunk, count - done);
+    SV_HIP(hipMemcpyAsync(host_out + 2 * done, (const float*)s->psi + 2 * (start + done), c * 8,
+                          hipMemcpyDeviceToHost, s->stream));
+  }
+  SV_HIP(hipStreamSynchronize(s->stream));
+  return SV_OK;
+  SV_GUARD_END(s)
+}
+
+int sv_write_amplitudes(sv_state* s, uint64_t start, uint64_t count, const float* host_in) {
+  if (int rc = check_handle(s)) return rc;
+  if (!host_in && count) return fail(SV_EINVAL, "host_in is NULL");
+  const uint64_t len = (uint64_t)1 << s->n;
+  if (start > len || count > len - start) return fail(SV_EINVAL, "amplitude range out of bounds");
+  SV_GUARD_BEGIN
+  SV_HIP(hipSetDevice(s->device));
+  const uint64_t chunk = (uint64_t)1 << 26;
+  for (uint64_t done = 0; done < count; done += chunk) {
+    const uint64_t c = std::min(chunk, count - done);
+    SV_HIP(hipMemcpyAsync((float*)s->psi + 2 * (start + done), host_in + 2 * done, c * 8, hipMemcpyHostToDevice,
+                          s->stream));
+  }
+  SV_HIP(hipStreamSynchronize(s->stream));
+  return SV_OK;
+  SV_GUARD_END(s)
+}
+
+}  // extern "C"
+
+// Accessors for the other translation units (batch, tuner).
+namespace sv {
+void* state_psi(sv_state* s) { return s->psi; }
+int state_n(sv_state* s) { return s->n; }
+hipStream_t state_stream(sv_state* s) { return s->stream; }
+bool state_poisoned(sv_state* s) { return s->poisoned; }
+void state_poison(sv_state* s) { s->poisoned = true; }
+}  // namespace sv

@@ -1,0 +1,173 @@
+// Gate fusion on the host in FP64 (Sec. II-C, Sec. IV-D).
+//
+// Vertical fusion multiplies gates on the same qubits; horizontal fusion
+// takes the tensor product of gates on disjoint qubits (Eq. 3).  Both come
+// out of one rule: a block is an ordered list of gates whose qubit union has
+// at most max_k qubits, and its matrix is the ordered product of its gates,
+// each lifted to the block's qubits.
+//
+// Greedy partition: seed a block with the earliest unconsumed gate and scan
+// forward.  A later gate joins when the union stays within max_k qubits and
+// none of its qubits is "blocked"; a gate that cannot join blocks all of its
+// qubits, because every later gate that touches them must stay behind it.
+// A joined gate therefore commutes with every skipped gate before it (they
+// share no qubit), so emitting the block at the seed's position and the
+// skipped gates after it preserves the circuit's action.
+#include <algorithm>
+#include <complex>
+#include <cstring>
+
+#include "sv_internal.h"
+
+namespace sv {
+
+using cd = std::complex<double>;
+
+int validate_gates(const sv_gate* g, size_t n, int n_qubits) {
+  if (n > 0 && !g) return fail(SV_EINVAL, "gates is NULL");
+  for (size_t i = 0; i < n; ++i) {
+    const int k = g[i].k;
+    if (k < 1 || k > SV_MAX_K || k > n_qubits)
+      return fail(SV_EINVAL, "gate " + std::to_string(i) + ": k=" + std::to_string(k) +
+                                 " outside 1..min(6, n)");
+    if (!g[i].matrix) return fail(SV_EINVAL, "gate " + std::to_string(i) + ": matrix is NULL");
+    for (int j = 0; j < k; ++j) {
+      const int q = g[i].qubits[j];
+      if (q < 0 || q >= n_qubits)
+        return fail(SV_EINVAL, "gate " + std::to_string(i) + ": qubit " + std::to_string(q) +
+                                   " out of range");
+      for (int a = 0; a < j; ++a)
+        if (g[i].qubits[a] == q)
+          return fail(SV_EINVAL, "gate " + std::to_string(i) + ": qubit " + std::to_string(q) +
+                                     " repeated");
+    }
+  }
+  return SV_OK;
+}
+
+static uint64_t qmask(const sv_gate& g) {
+  uint64_t m = 0;
+  for (int j = 0; j < g.k; ++j) m |= (uint64_t)1 << g.qubits[j];
+  return m;
+}
+
+// M <- G M, where M is the 2^K x 2^K block matrix (row-major) and G acts on
+// block-local bits pos[0..k-1] (local bit j of G = block bit pos[j]).
+static void left_multiply(std::vector<cd>& M, int K, const sv_gate& g, const int* pos) {
+  const int d = 1 << K, k = g.k, dk = 1 << k;
+  std::vector<int> sorted(pos, pos + k);
+  std::sort(sorted.begin(), sorted.end());
+  std::vector<int> off(dk);
+  for (int l = 0; l < dk; ++l) {
+    int o = 0;
+    for (int j = 0; j < k; ++j)
+      if ((l >> j) & 1) o |= 1 << pos[j];
+    off[l] = o;
+  }
+  std::vector<cd> u(dk * dk);
+  for (int i = 0; i < dk * dk; ++i) u[i] = cd(g.matrix[2 * i], g.matrix[2 * i + 1]);
+  std::vector<cd> v(dk);
+  for (int grp = 0; grp < (d >> k); ++grp) {
+    int base = grp;
+    for (int j = 0; j < k; ++j) {
+      const int lm = (1 << sorted[j]) - 1;
+      base = ((base & ~lm) << 1) | (base & lm);
+    }
+    for (int col = 0; col < d; ++col) {
+      for (int l = 0; l < dk; ++l) v[l] = M[(size_t)(base + off[l]) * d + col];
+      for (int r = 0; r < dk; ++r) {
+        cd acc = 0.0;
+        for (int c = 0; c < dk; ++c) acc += u[r * dk + c] * v[c];
+        M[(size_t)(base + off[r]) * d + col] = acc;
+      }
+    }
+  }
+}
+
+// Build the fused gate of an ordered member list.
+static void build_block(const sv_gate* g, const std::vector<int>& members, FusedGate& out) {
+  uint64_t S = 0;
+  for (int i : members) S |= qmask(g[i]);
+  int K = 0;
+  int bitpos[64];
+  for (int q = 0; q < 64; ++q)
+    if ((S >> q) & 1) {
+      bitpos[q] = K;
+      out.q[K++] = q;
+    }
+  out.k = K;
+  const int d = 1 << K;
+  std::vector<cd> M((size_t)d * d, 0.0);
+  for (int i = 0; i < d; ++i) M[(size_t)i * d + i] = 1.0;
+  for (int i : members) {
+    int pos[SV_MAX_K];
+    for (int j = 0; j < g[i].k; ++j) pos[j] = bitpos[g[i].qubits[j]];
+    left_multiply(M, K, g[i], pos);
+  }
+  out.mat.resize((size_t)2 * d * d);
+  for (size_t i = 0; i < (size_t)d * d; ++i) {
+    out.mat[2 * i] = M[i].real();
+    out.mat[2 * i + 1] = M[i].imag();
+  }
+}
+
+void fuse_none(const sv_gate* g, size_t n, std::vector<FusedGate>& out, std::vector<int32_t>& block_of) {
+  out.clear();
+  out.reserve(n);
+  block_of.assign(n, 0);
+  for (size_t i = 0; i < n; ++i) {
+    FusedGate f;
+    f.k = g[i].k;
+    normalise_gate(g[i].k, g[i].qubits, g[i].matrix, f.q, f.mat);
+    out.push_back(std::move(f));
+    block_of[i] = (int32_t)i;
+  }
+}
+
+// Greedy partition into member lists (indices into g), blocks in emission order.
+void greedy_partition(const sv_gate* g, size_t n, int max_k, std::vector<std::vector<int>>& blocks) {
+  blocks.clear();
+  std::vector<uint64_t> masks(n);
+  for (size_t i = 0; i < n; ++i) masks[i] = qmask(g[i]);
+  std::vector<char> consumed(n, 0);
+  for (size_t seed = 0; seed < n; ++seed) {
+    if (consumed[seed]) continue;
+    std::vector<int> members{(int)seed};
+    consumed[seed] = 1;
+    uint64_t S = masks[seed], blocked = 0;
+    for (size_t h = seed + 1; h < n; ++h) {
+      if (consumed[h]) continue;
+      const uint64_t qh = masks[h];
+      if ((qh & blocked) == 0 && __builtin_popcountll(S | qh) <= max_k) {
+        S |= qh;
+        members.push_back((int)h);
+        consumed[h] = 1;
+      } else {
+        blocked |= qh;
+      }
+      // no later gate can join once the block is full and all its qubits are blocked
+      if (__builtin_popcountll(S) >= max_k && (S & ~blocked) == 0) break;
+    }
+    blocks.push_back(std::move(members));
+  }
+}
+
+void fuse_blocks(const sv_gate* g, size_t n, const std::vector<std::vector<int>>& blocks,
+                 std::vector<FusedGate>& out, std::vector<int32_t>& block_of) {
+  out.clear();
+  out.resize(blocks.size());
+  block_of.assign(n, -1);
+  for (size_t b = 0; b < blocks.size(); ++b) {
+    build_block(g, blocks[b], out[b]);
+    for (int i : blocks[b]) block_of[i] = (int32_t)b;
+  }
+}
+
+void fuse_greedy(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>& out,
+                 std::vector<int32_t>& block_of) {
+  std::vector<std::vector<int>> blocks;
+  greedy_partition(g, n, max_k, blocks);
+  fuse_blocks(g, n, blocks, out, block_of);
+}
+
+}  // namespace sv

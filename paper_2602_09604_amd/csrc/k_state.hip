@@ -1,0 +1,114 @@
+// State initialisation and the FP64 norm reduction sum |c_i|^2 (Eq. 1).
+#include "sv_internal.h"
+
+namespace sv {
+
+namespace {
+
+constexpr int kNormBlocks = 2048;  // partials of the first level
+constexpr int kThreads = 256;
+
+// Write |index>: a single coalesced sweep of 16-byte stores.
+__global__ __launch_bounds__(256) void k_init_basis(float4* __restrict__ psi, uint64_t pairs,
+                                                    uint64_t index) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < pairs; i += stride) {
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (i == (index >> 1)) {
+      if (index & 1) v.z = 1.f;
+      else v.x = 1.f;
+    }
+    psi[i] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_init_basis_1q(float2* __restrict__ psi, uint64_t index) {
+  if (threadIdx.x < 2) psi[threadIdx.x] = make_float2(threadIdx.x == index ? 1.f : 0.f, 0.f);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+__device__ double block_sum(double v) {
+  __shared__ double part[kThreads / 64];
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) part[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kThreads / 64; ++i) s += part[i];
+  return s;
+}
+
+// Level 1: each block owns a contiguous slice of float4 pairs; FP32 squares
+// promoted to FP64 before accumulation.
+__global__ __launch_bounds__(256) void k_norm_partial(const float4* __restrict__ psi, uint64_t pairs,
+                                                      double* __restrict__ partials) {
+  const uint64_t per = (pairs + gridDim.x - 1) / gridDim.x;
+  const uint64_t lo = (uint64_t)blockIdx.x * per;
+  const uint64_t hi = lo + per < pairs ? lo + per : pairs;
+  double acc = 0.0;
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
+    const float4 v = psi[i];
+    acc = fma((double)v.x, (double)v.x, acc);
+    acc = fma((double)v.y, (double)v.y, acc);
+    acc = fma((double)v.z, (double)v.z, acc);
+    acc = fma((double)v.w, (double)v.w, acc);
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// Level 2: one block sums the partials in a fixed order.
+__global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ partials, int parts,
+                                                    double* __restrict__ out) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < parts; i += kThreads) acc += partials[i];
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) *out = s;
+}
+
+__global__ void k_norm_1q(const float2* __restrict__ psi, double* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < 2; ++i) s += (double)psi[i].x * psi[i].x + (double)psi[i].y * psi[i].y;
+    *out = s;
+  }
+}
+
+}  // namespace
+
+int norm_partials_needed() { return kNormBlocks; }
+
+void launch_init_basis(void* psi, int n, uint64_t index, hipStream_t st) {
+  if (n == 1) {
+    hipLaunchKernelGGL(k_init_basis_1q, dim3(1), dim3(64), 0, st, (float2*)psi, index);
+  } else {
+    const uint64_t pairs = (uint64_t)1 << (n - 1);
+    uint64_t blocks = (pairs + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_init_basis, dim3((unsigned)blocks), dim3(256), 0, st, (float4*)psi, pairs, index);
+  }
+  SV_HIP(hipGetLastError());
+}
+
+void launch_norm(const void* psi, int n, double* partials, int max_parts, double* out, hipStream_t st) {
+  if (n == 1) {
+    hipLaunchKernelGGL(k_norm_1q, dim3(1), dim3(64), 0, st, (const float2*)psi, out);
+  } else {
+    const uint64_t pairs = (uint64_t)1 << (n - 1);
+    uint64_t blocks = (pairs + 1023) / 1024;  // at least 4 pairs per thread
+    if (blocks > (uint64_t)max_parts) blocks = max_parts;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_norm_partial, dim3((unsigned)blocks), dim3(256), 0, st, (const float4*)psi, pairs,
+                       partials);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, st, (const double*)partials, (int)blocks, out);
+  }
+  SV_HIP(hipGetLastError());
+}
+
+}  // namespace sv

@@ -1,0 +1,78 @@
+// Host planning of passes: target normalisation, variant choice, LDS tile
+// split, and the encoding of a pass's matrix for the device.
+#include <algorithm>
+#include <cstring>
+
+#include "sv_internal.h"
+
+namespace sv {
+
+// Sort the targets ascending and permute the matrix to match: new local bit j
+// is state bit sorted[j]; old local index = sum_j bit_j(new) << perm[j].
+void normalise_gate(int k, const int32_t* qubits, const double* mat, int* sorted_out,
+                    std::vector<double>& mat_out) {
+  int perm[SV_MAX_K];
+  for (int j = 0; j < k; ++j) perm[j] = j;
+  std::sort(perm, perm + k, [&](int a, int b) { return qubits[a] < qubits[b]; });
+  for (int j = 0; j < k; ++j) sorted_out[j] = qubits[perm[j]];
+  const int d = 1 << k;
+  std::vector<int> old_of(d);
+  for (int l = 0; l < d; ++l) {
+    int o = 0;
+    for (int j = 0; j < k; ++j)
+      if ((l >> j) & 1) o |= 1 << perm[j];
+    old_of[l] = o;
+  }
+  mat_out.assign((size_t)2 * d * d, 0.0);
+  for (int r = 0; r < d; ++r)
+    for (int c = 0; c < d; ++c) {
+      const size_t src = (size_t)2 * (old_of[r] * d + old_of[c]);
+      const size_t dst = (size_t)2 * (r * d + c);
+      mat_out[dst] = mat[src];
+      mat_out[dst + 1] = mat[src + 1];
+    }
+}
+
+// Number h of targets that fall at or above the chunk boundary m = T - h
+// (the fixed point exists because #targets >= m is non-increasing in m).
+int lds_split(int tile_bits, int k, const int* s, int* m_out) {
+  for (int h = 0; h <= k; ++h) {
+    const int m = tile_bits - h;
+    int c = 0;
+    for (int j = 0; j < k; ++j)
+      if (s[j] >= m) ++c;
+    if (c == h) {
+      *m_out = m;
+      return h;
+    }
+  }
+  *m_out = tile_bits - k;
+  return k;
+}
+
+// A target in bits 1..6 breaks the 1 KiB contiguous wavefront row of the
+// register kernel (bit 0 is handled inside its 16-byte element).
+static bool has_low_target(int k, const int* s) {
+  for (int j = 0; j < k; ++j)
+    if (s[j] >= 1 && s[j] < 7) return true;
+  return false;
+}
+
+static bool lds_feasible(int n, int k, const int* s, int tile_bits) {
+  const int T = std::min(tile_bits, n);
+  int m = 0;
+  lds_split(T, k, s, &m);
+  return n >= 8 && m >= 1 && T - k >= 0;
+}
+
+int choose_variant(int n, int k, const int* s, int precision, int requested) {
+  const Shape sh = tuned_shape(V_LDS, n, k, s, precision);
+  if (requested == V_MFMA) return mfma_supported(k, precision) && n >= k + 6 ? V_MFMA : V_REG;
+  if (requested == V_LDS) return lds_feasible(n, k, s, sh.tile_bits) ? V_LDS : V_REG;
+  if (requested == V_REG) return V_REG;
+  if (precision != SV_PREC_FP32_VALU && k >= 4 && mfma_supported(k, precision) && n >= k + 6) return V_MFMA;
+  if (has_low_target(k, s) && lds_feasible(n, k, s, sh.tile_bits)) return V_LDS;
+  return V_REG;
+}
+
+}  // namespace sv

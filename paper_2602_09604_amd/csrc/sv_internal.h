@@ -1,0 +1,94 @@
+// Internal declarations shared by the library's translation units (not part
+// of the ABI).  Conventions: qubit q = bit q of the amplitude index; a pass's
+// targets are held sorted ascending (s[0] < s[1] < ...) and its matrix has
+// been permuted to match, so local bit j of the matrix index is state bit s[j].
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sv.h"
+
+namespace sv {
+
+// ---------------------------------------------------------------- errors --
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+struct DeviceError {
+  hipError_t err;
+  const char* what;
+};
+
+#define SV_HIP(call)                                          \
+  do {                                                        \
+    hipError_t e_ = (call);                                   \
+    if (e_ != hipSuccess) throw ::sv::DeviceError{e_, #call}; \
+  } while (0)
+
+// ---------------------------------------------------------------- passes --
+// One in-place sweep of the state by a k-qubit gate.
+enum Variant { V_AUTO = 0, V_REG = 1, V_LDS = 2, V_MFMA = 3 };
+
+struct Pass {
+  int k = 0;
+  int s[SV_MAX_K] = {0, 0, 0, 0, 0, 0};  // sorted targets
+  int variant = V_REG;                   // resolved (never AUTO)
+  int precision = SV_PREC_FP32_VALU;
+  size_t mat_off = 0;                    // byte offset of the pass data in the matrix arena
+  size_t mat_bytes = 0;
+  // launch shape (from the tuner or defaults)
+  int tile_bits = 13;                    // LDS: log2 amplitudes per tile
+  int reg_iters = 1;                     // REG: groups per thread
+  int mfma_cols = 32;                    // MFMA: groups per wavefront tile
+};
+
+// Launch shape defaults / tuned values.
+struct Shape {
+  int tile_bits = 13;
+  int reg_iters = 1;
+  int mfma_cols = 32;
+};
+
+// Kernel launchers (k_apply.hip, k_mfma.hip, k_state.hip).
+void launch_pass(const Pass& p, int n, void* psi, const unsigned char* arena_dev, hipStream_t st);
+void launch_init_basis(void* psi, int n, uint64_t index, hipStream_t st);
+void launch_norm(const void* psi, int n, double* partials, int max_parts, double* out, hipStream_t st);
+int norm_partials_needed();
+
+// Bytes of device data a pass needs in the arena for its precision/variant,
+// and the host-side encoder that writes it (matrix already normalised,
+// complex128 row-major in sorted-target order).
+size_t pass_data_bytes(const Pass& p);
+void encode_pass_data(const Pass& p, const double* mat, unsigned char* dst);
+bool mfma_supported(int k, int precision);
+
+// Planning helpers (plan.cpp).
+void normalise_gate(int k, const int32_t* qubits, const double* mat, int* sorted_out,
+                    std::vector<double>& mat_out);
+int choose_variant(int n, int k, const int* s, int precision, int requested);
+Shape tuned_shape(int variant, int n, int k, const int* s, int precision);
+int lds_split(int tile_bits, int k, const int* s, int* m_out);
+
+// Fusion (fuse.cpp).
+struct FusedGate {
+  int k;
+  int q[SV_MAX_K];             // ascending
+  std::vector<double> mat;     // 2 * 4^k doubles, row-major, local bit j = q[j]
+};
+int validate_gates(const sv_gate* g, size_t n, int n_qubits);
+void fuse_greedy(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>& out,
+                 std::vector<int32_t>& block_of);
+void fuse_none(const sv_gate* g, size_t n, std::vector<FusedGate>& out, std::vector<int32_t>& block_of);
+bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int precision,
+                  std::vector<FusedGate>& out, std::vector<int32_t>& block_of);
+
+// Cost model (cost_model.cpp).
+void cost_features(int k, const int* qubits, int n, int precision, float* out);
+bool cost_model_ready();
+double cost_model_predict_log(int k, const int* qubits, int n, int precision);
+
+}  // namespace sv

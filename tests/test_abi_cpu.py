@@ -1,0 +1,195 @@
+"""Host-side checks of libsv.so that need no GPU: exported symbols, the FP64
+fusion pass (checked through the oracle), validation and error codes."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import circuits as C
+import oracle
+from paper_2602_09604_amd import sv
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+needs_lib = pytest.mark.skipif(not os.path.exists(sv.LIB_PATH), reason="libsv.so not built")
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "sv.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sv_[a-z0-9_]+)\s*\(", text)))
+
+
+@needs_lib
+def test_library_exports_every_declared_symbol():
+    names = header_functions()
+    assert len(names) >= 30
+    L = ctypes.CDLL(sv.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(names) == set(sv.exported_symbols())
+
+
+@needs_lib
+def test_version_and_last_error():
+    assert b"libsv" in sv.lib().sv_version()
+    assert isinstance(sv.lib().sv_last_error(), bytes)
+
+
+# --------------------------------------------------------------------------
+# Fusion (host FP64), checked against the unfused oracle
+# --------------------------------------------------------------------------
+def _check_partition(gates, fused, block_of, max_k):
+    assert len(block_of) == len(gates)
+    assert set(block_of.tolist()) == set(range(len(fused)))
+    for f in fused:
+        assert 1 <= f.k <= max_k
+        assert list(f.qubits) == sorted(f.qubits)
+    for i, g in enumerate(gates):  # every gate's qubits are inside its block
+        assert set(g.qubits) <= set(fused[block_of[i]].qubits)
+    n = max(q for g in gates for q in g.qubits) + 1
+    for q in range(n):  # per-qubit program order is preserved
+        seq = [int(block_of[i]) for i, g in enumerate(gates) if q in g.qubits]
+        assert seq == sorted(seq)
+
+
+@needs_lib
+@pytest.mark.parametrize("max_k", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_greedy_fusion_equivalent(max_k, seed):
+    n = 9
+    gates = C.random_circuit(n, 40, max_k=min(2, max_k), seed=seed)
+    fused, block_of = sv.sv_fuse(gates, n, sv.make_opts(max_k=max_k, fusion="greedy"))
+    _check_partition(gates, fused, block_of, max_k)
+    ref = oracle.apply_circuit(n, gates, init=seed)
+    got = oracle.apply_circuit(n, fused, init=seed)
+    assert np.max(np.abs(ref - got)) < 1e-12
+    if max_k >= 2:
+        assert len(fused) < len(gates)
+
+
+@needs_lib
+def test_greedy_fusion_grid_circuit():
+    gates = C.grid_circuit(2, 5, 8, seed=1)
+    n = 10
+    ref = oracle.apply_circuit(n, gates)
+    for K in (2, 4, 6):
+        fused, block_of = sv.sv_fuse(gates, n, sv.make_opts(max_k=K))
+        _check_partition(gates, fused, block_of, K)
+        assert np.max(np.abs(oracle.apply_circuit(n, fused) - ref)) < 1e-12
+
+
+@needs_lib
+def test_fusion_vertical_product():
+    """Two gates on the same qubit fuse into their matrix product (later gate on the left)."""
+    rng = np.random.Generator(np.random.PCG64(0))
+    a, b = C.haar_unitary(1, rng), C.haar_unitary(1, rng)
+    fused, _ = sv.sv_fuse([C.Gate((3,), a), C.Gate((3,), b)], 5, sv.make_opts(max_k=1))
+    assert len(fused) == 1
+    assert np.allclose(fused[0].matrix, b @ a, atol=1e-15)
+
+
+@needs_lib
+def test_fusion_horizontal_tensor_product():
+    """Eq. 3: gates on disjoint qubits fuse into the Kronecker product
+    (ascending qubits, local bit 0 = lowest qubit = low Kronecker factor)."""
+    rng = np.random.Generator(np.random.PCG64(1))
+    a, b = C.haar_unitary(1, rng), C.haar_unitary(1, rng)
+    fused, _ = sv.sv_fuse([C.Gate((4,), a), C.Gate((1,), b)], 6, sv.make_opts(max_k=2))
+    assert len(fused) == 1 and fused[0].qubits == (1, 4)
+    assert np.allclose(fused[0].matrix, np.kron(a, b), atol=1e-15)
+
+
+@needs_lib
+def test_fusion_none_sorts_targets():
+    rng = np.random.Generator(np.random.PCG64(2))
+    u = C.haar_unitary(3, rng)
+    g = C.Gate((5, 0, 2), u)
+    fused, block_of = sv.sv_fuse([g], 6, sv.make_opts(fusion="none"))
+    assert fused[0].qubits == (0, 2, 5)
+    a = oracle.apply_circuit(6, [g], init=13)
+    b = oracle.apply_circuit(6, fused, init=13)
+    assert np.max(np.abs(a - b)) < 1e-15
+
+
+@needs_lib
+def test_fusion_respects_blocking():
+    """CNOT(0,1), H(1), X(0) with max_k = 1: H(1) cannot pass CNOT, so the
+    single-qubit gates stay in separate blocks after it."""
+    gates = [C.Gate((0, 1), C.CNOT), C.Gate((1,), C.H), C.Gate((0,), C.X)]
+    fused, block_of = sv.sv_fuse(gates, 2, sv.make_opts(max_k=2))
+    assert len(fused) == 1
+    ref = oracle.apply_circuit(2, gates, init=1)
+    assert np.max(np.abs(oracle.apply_circuit(2, fused, init=1) - ref)) < 1e-15
+
+
+@needs_lib
+def test_fusion_empty():
+    fused, block_of = sv.sv_fuse([], 4, sv.make_opts())
+    assert fused == [] and len(block_of) == 0
+
+
+# --------------------------------------------------------------------------
+# Validation
+# --------------------------------------------------------------------------
+@needs_lib
+@pytest.mark.parametrize("gate,n", [
+    (C.Gate((5,), C.H), 5),            # qubit out of range
+    (C.Gate((-1,), C.H), 5),
+    (C.Gate((1, 1), C.CZ), 5),         # repeated qubit
+    (C.Gate((0, 1, 2), np.eye(8)), 2),  # k > n
+])
+def test_fuse_rejects_invalid_gates(gate, n):
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_fuse([gate], n, sv.make_opts())
+    assert e.value.code == sv.SV_EINVAL
+
+
+@needs_lib
+def test_fuse_rejects_bad_opts():
+    with pytest.raises(sv.SvError):
+        sv.sv_fuse([C.Gate((0,), C.H)], 2, sv.make_opts(max_k=7))
+    o = sv.make_opts()
+    o.timing = 2
+    with pytest.raises(sv.SvError):
+        sv.sv_fuse([C.Gate((0,), C.H)], 2, o)
+
+
+@needs_lib
+def test_fuse_rejects_k7_and_null_matrix():
+    ga = sv.GateArray([C.Gate((0,), C.H)])
+    ga.arr[0].k = 7
+    out = ctypes.POINTER(sv.sv_gate)()
+    n_out = ctypes.c_size_t()
+    rc = sv.lib().sv_fuse(ga.ptr, 1, 8, None, ctypes.byref(out), ctypes.byref(n_out), None)
+    assert rc == sv.SV_EINVAL
+    ga = sv.GateArray([C.Gate((0,), C.H)])
+    ga.arr[0].matrix = ctypes.cast(None, ctypes.POINTER(ctypes.c_double))
+    rc = sv.lib().sv_fuse(ga.ptr, 1, 8, None, ctypes.byref(out), ctypes.byref(n_out), None)
+    assert rc == sv.SV_EINVAL
+    assert b"NULL" in sv.lib().sv_last_error()
+
+
+@needs_lib
+def test_null_handle_calls_fail_cleanly():
+    L = sv.lib()
+    assert L.sv_set_basis(None, 0) == sv.SV_EINVAL
+    assert L.sv_norm(None, None) == sv.SV_EINVAL
+    assert L.sv_free(None) == sv.SV_OK
+    h = ctypes.c_void_p()
+    assert L.sv_alloc(0, 0, ctypes.c_void_p(16), 1 << 20, None, ctypes.byref(h)) == sv.SV_EINVAL
+    assert L.sv_alloc(41, 0, ctypes.c_void_p(16), 1 << 20, None, ctypes.byref(h)) == sv.SV_EINVAL
+    assert L.sv_alloc(10, 1, ctypes.c_void_p(16), 1 << 20, None, ctypes.byref(h)) == sv.SV_EINVAL
+    # buffer too small is rejected before any device call
+    assert L.sv_alloc(20, 0, ctypes.c_void_p(16), 1 << 20, None, ctypes.byref(h)) == sv.SV_ENOMEM
+
+
+@needs_lib
+def test_cost_features_layout():
+    f = sv.sv_cost_features(3, [0, 5, 33], 34, sv.SV_PREC_BF16X3)
+    assert f.shape == (40,)
+    assert abs(f[0] - 0.5) < 1e-7 and abs(f[1] - 1.0) < 1e-7
+    assert f[2 + 0] == 1 and f[2 + 5] == 1 and f[2 + 33] == 1 and f[2:36].sum() == 3
+    assert f[36:40].tolist() == [0, 0, 1, 0]

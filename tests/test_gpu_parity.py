@@ -1,0 +1,208 @@
+"""GPU parity: the HIP path through the C ABI against the CPU complex128 oracle.
+
+Bar (complex64 state, FP32 arithmetic): max |delta amplitude| <= 1e-5 and
+infidelity <= 1e-6 against the oracle, on the same seeded inputs.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import circuits as C
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+MAX_ABS = 1e-5
+INFID = 1e-6
+
+
+def _sv():
+    from paper_2602_09604_amd import sv
+    return sv
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def check(psi_gpu, psi_ref, max_abs=MAX_ABS, infid=INFID):
+    r = oracle.compare(psi_gpu, psi_ref)
+    assert r["max_abs"] <= max_abs, r
+    assert r["infidelity"] <= infid, r
+    return r
+
+
+def run_gpu(n, gates, init=0, **kw):
+    sv = _sv()
+    st = sv.State(n)
+    try:
+        if init:
+            st.set_basis(init)
+        st.apply_circuit(gates, **kw)
+        return st.read()
+    finally:
+        st.free()
+
+
+def random_state_circuit(n, seed):
+    """A prefix circuit that spreads amplitude over the whole state."""
+    rng = np.random.Generator(np.random.PCG64(1000 + seed))
+    return [C.Gate((q,), C.haar_unitary(1, rng)) for q in range(n)]
+
+
+TARGET_SETS = {
+    # name: function (n, k) -> qubits (unsorted on purpose)
+    "low_q0": lambda n, k: tuple(reversed(range(k))),
+    "high_top": lambda n, k: tuple(range(n - 1, n - 1 - k, -1)),
+    "mixed": lambda n, k: tuple(sorted({0, n - 1, *range(2, 2 + max(0, k - 2))}, key=lambda q: (q * 7) % 11))[:k],
+    "mid": lambda n, k: tuple(range(3, 3 + k)),
+    "low_no_q0": lambda n, k: tuple(range(1, 1 + k)),
+}
+
+
+@pytest.mark.parametrize("variant", ["reg", "lds", "auto"])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("tname", list(TARGET_SETS))
+def test_single_gate_variants(variant, k, tname):
+    n = 14
+    qs = TARGET_SETS[tname](n, k)
+    assert len(set(qs)) == k and all(0 <= q < n for q in qs)
+    rng = np.random.Generator(np.random.PCG64(k * 100 + len(tname)))
+    gates = random_state_circuit(n, k) + [C.Gate(qs, C.haar_unitary(k, rng))]
+    say("single gate", variant, k, tname, qs)
+    got = run_gpu(n, gates, fusion="none", variant=variant)
+    check(got, oracle.apply_circuit(n, gates))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7, 8, 9, 12])
+def test_small_states_every_k(n):
+    """Ragged sizes including n == k (every qubit a target) and n = 1."""
+    for k in range(1, min(6, n) + 1):
+        gates = random_state_circuit(n, n) + C.random_circuit(n, 6, max_k=k, min_k=k, seed=n * 10 + k)
+        say("small", n, k)
+        for variant in ("auto", "reg", "lds"):
+            got = run_gpu(n, gates, fusion="none", variant=variant)
+            check(got, oracle.apply_circuit(n, gates))
+
+
+def test_config1_grid_unfused_full_state():
+    """20-qubit 4x5 grid, depth 14, unfused: the plain FP32 baseline circuit."""
+    n = 20
+    gates = C.grid_circuit(4, 5, 14, seed=0)
+    ref = oracle.apply_circuit(n, gates)
+    for graph in (False, True):
+        say("config1 graph", graph)
+        got = run_gpu(n, gates, fusion="none", precision="fp32_valu", use_graph=graph)
+        r = check(got, ref)
+        say(r)
+
+
+@pytest.mark.parametrize("max_k", [2, 3, 4, 5, 6])
+def test_grid_fused_greedy(max_k):
+    n = 20
+    gates = C.grid_circuit(4, 5, 14, seed=1)
+    ref = oracle.apply_circuit(n, gates)
+    say("grid fused", max_k)
+    check(run_gpu(n, gates, max_k=max_k, fusion="greedy"), ref)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_circuits_fused(seed):
+    n = 16 + seed
+    gates = C.random_circuit(n, 60, max_k=3, seed=seed)
+    ref = oracle.apply_circuit(n, gates, init=seed)
+    for K in (3, 5):
+        say("random fused", n, K)
+        check(run_gpu(n, gates, init=seed, max_k=K), ref)
+
+
+def test_ghz_closed_form_26():
+    n = 26
+    sv = _sv()
+    st = sv.State(n)
+    try:
+        st.apply_circuit(C.ghz_circuit(n), fusion="none")
+        idx = np.array([0, 1, 2, (1 << n) - 2, (1 << n) - 1, 12345, 1 << 25])
+        got = np.array([st.read(int(i), 1)[0] for i in idx])
+        assert np.max(np.abs(got - oracle.ghz_amplitudes(n, idx))) < 1e-6
+        assert abs(st.norm() - 1) < 1e-6
+    finally:
+        st.free()
+
+
+def test_qft_like_closed_form_24():
+    n = 24
+    x = C.qft_input_basis(n, 3)
+    sv = _sv()
+    st = sv.State(n)
+    try:
+        st.set_basis(x)
+        st.apply_circuit(C.qft_like_circuit(n), max_k=5)
+        psi = st.read()
+        ref = oracle.qft_like_amplitudes(n, x, np.arange(1 << n))
+        check(psi, ref)
+    finally:
+        st.free()
+
+
+def test_norm_and_basis():
+    sv = _sv()
+    st = sv.State(12)
+    try:
+        assert st.norm() == 1.0
+        st.set_basis(777)
+        a = st.read()
+        assert a[777] == 1 and np.count_nonzero(a) == 1
+        v = (np.arange(1 << 12) % 7 + 1j * (np.arange(1 << 12) % 5)).astype(np.complex64)
+        st.write(0, v)
+        assert abs(st.norm() - float(np.sum(np.abs(v.astype(np.complex128)) ** 2))) < 1e-9 * np.sum(np.abs(v) ** 2)
+        assert np.array_equal(st.read(100, 50), v[100:150])
+    finally:
+        st.free()
+
+
+def test_validation_leaves_state_untouched():
+    sv = _sv()
+    st = sv.State(10)
+    try:
+        st.set_basis(5)
+        for bad in ([C.Gate((10,), C.H)], [C.Gate((1, 1), C.CZ)], [C.Gate((0,), C.H), C.Gate((0, 1, 2, 3, 4, 5, 6), np.eye(128))]):
+            with pytest.raises(sv.SvError) as e:
+                st.apply_circuit(bad)
+            assert e.value.code == sv.SV_EINVAL
+        with pytest.raises(sv.SvError):
+            sv.sv_read_amplitudes(st.h, 1000, 100)
+        a = st.read()
+        assert a[5] == 1 and np.count_nonzero(a) == 1
+    finally:
+        st.free()
+
+
+def test_apply_gate_entry_point():
+    n = 11
+    rng = np.random.Generator(np.random.PCG64(4))
+    gates = random_state_circuit(n, 2) + [C.Gate((7, 2, 0), C.haar_unitary(3, rng)), C.Gate((10,), C.H)]
+    sv = _sv()
+    st = sv.State(n)
+    try:
+        for g in gates:
+            st.apply_gate(g.qubits, g.matrix)
+        check(st.read(), oracle.apply_circuit(n, gates))
+    finally:
+        st.free()
+
+
+def test_many_small_gates_wrap_the_arena():
+    """More single-gate uploads than the staging ring holds."""
+    n = 10
+    gates = C.random_circuit(n, 900, max_k=6, min_k=6, seed=5)
+    sv = _sv()
+    st = sv.State(n)
+    try:
+        for g in gates:
+            st.apply_gate(g.qubits, g.matrix)
+        check(st.read(), oracle.apply_circuit(n, gates), max_abs=1e-4, infid=1e-5)
+    finally:
+        st.free()

@@ -1,0 +1,84 @@
+// Gate-application passes on VALU (gfx950): each pass applies one k-qubit
+// matrix to all 2^(n-k) groups of the state in place (Sec. II-A, Eq. 4).
+//
+// Two kernels:
+//   k_apply_reg  -- every lane owns whole groups in registers, gathered
+//                   straight from HBM.  Lanes are consecutive in the lowest
+//                   non-target bits, so each of the 2^K loads of a wavefront
+//                   is one contiguous row when no target sits in bits 1..6.
+//                   All amplitudes of a group are loaded before the first
+//                   output is written (the load-buffer idea of Sec. IV-B), so
+//                   each output row is stored as soon as it is computed.
+//   k_apply_lds  -- a workgroup copies a tile of 2^T amplitudes (2^h chunks of
+//                   2^m contiguous amplitudes, one chunk per combination of the
+//                   h targets >= m) into LDS with coalesced 16-byte loads,
+//                   applies the gate to the 2^(T-k) groups of the tile from
+//                   LDS, and writes the tile back coalesced.  This is the
+//                   path for targets in the low bits, where a register-direct
+//                   gather would touch partial cache lines.
+//
+// Matrix entries are wave-uniform and read through the scalar unit; the
+// matrix of a pass sits in the device arena, complex64 row-major, already
+// permuted so that local bit j is the j-th lowest target.
+#pragma once
+#include "sv_internal.h"
+
+namespace sv {
+namespace kern {
+
+__device__ __forceinline__ void cmac(float2& acc, const float2 u, const float2 v) {
+  acc.x = fmaf(u.x, v.x, acc.x);
+  acc.x = fmaf(-u.y, v.y, acc.x);
+  acc.y = fmaf(u.x, v.y, acc.y);
+  acc.y = fmaf(u.y, v.x, acc.y);
+}
+
+// Insert a zero bit below each mask boundary, ascending: turns a group index
+// into the index of its first amplitude (all target bits zero).
+template <int K, typename IDX>
+__device__ __forceinline__ IDX insert_zeros(IDX g, const IDX* lowmask) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) g = ((g & ~lowmask[j]) << 1) | (g & lowmask[j]);
+  return g;
+}
+
+template <int K, typename IDX>
+__device__ __forceinline__ IDX local_offset(int l, const IDX* stride) {
+  IDX off = 0;
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+    if ((l >> j) & 1) off += stride[j];
+  return off;
+}
+
+// Output row r of the pair layout.  MODE 0: v[c] holds local index c of two
+// groups (bit 0 = 0 in .xy, bit 0 = 1 in .zw); MODE 1: v[c] holds local
+// indices 2c (.xy) and 2c+1 (.zw) of one group, and the result holds rows
+// 2r and 2r+1.
+template <int K, int MODE>
+__device__ __forceinline__ float4 pair_row(const float4* v, const float2* __restrict__ U, const int r) {
+  constexpr int D = 1 << K;
+  float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
+  if constexpr (MODE == 0) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const float2 u = U[r * D + c];
+      cmac(a0, u, make_float2(v[c].x, v[c].y));
+      cmac(a1, u, make_float2(v[c].z, v[c].w));
+    }
+  } else {
+    constexpr int DM = 2 * D;  // matrix dimension 2^(K+1)
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const float2 lo = make_float2(v[c].x, v[c].y), hi = make_float2(v[c].z, v[c].w);
+      cmac(a0, U[(2 * r) * DM + 2 * c], lo);
+      cmac(a0, U[(2 * r) * DM + 2 * c + 1], hi);
+      cmac(a1, U[(2 * r + 1) * DM + 2 * c], lo);
+      cmac(a1, U[(2 * r + 1) * DM + 2 * c + 1], hi);
+    }
+  }
+  return make_float4(a0.x, a0.y, a1.x, a1.y);
+}
+
+}  // namespace kern
+}  // namespace sv

@@ -1,17 +1,362 @@
 // Matrix-core passes for fused gates with k >= 4.
+//
+// The group matvecs of one pass (Eq. 4) are batched into a real GEMM in the
+// 4M form: with rows ordered (amplitude, re/im), the 2^(k+1) x 2^(k+1) real
+// matrix A' has blocks [[Ur, -Ui], [Ui, Ur]] and Y' = A' X', where column m of
+// X' is one group's 2^k amplitudes.  The state is the B operand: each lane
+// owns one column (or, in the PAIR layout, two columns that differ only in
+// bit 0, fetched with one 16-byte load per amplitude), so the gathers stay
+// coalesced 16-byte loads and the results leave as 16-byte stores.
+//
+// A' is encoded on the host in MFMA fragment order and copied once per
+// workgroup into LDS; every wave then streams 32-group tiles through it.
+//
+//   FP32_MFMA: v_mfma_f32_32x32x2f32, one product.
+//   BF16X3:    operands split into bf16 hi + lo (lo = bf16(x - hi)); three
+//              v_mfma_f32_32x32x16_bf16 products hi*hi + hi*lo + lo*hi,
+//              FP32 accumulation.
+//   FP16X3:    as BF16X3 in fp16 with the lo halves scaled by 2^11, amplitudes
+//              scaled by 2^14 before the split (every amplitude of a
+//              normalised state, |c| <= 1, stays below the fp16 maximum and
+//              amplitudes down to ~4e-9 stay normal); two FP32 accumulators
+//              (hi*hi and the 2^11-scaled cross terms) combined at the end.
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+
 #include "sv_internal.h"
 
 namespace sv {
 
-bool mfma_supported(int k, int precision) { (void)k; (void)precision; return false; }
-size_t mfma_data_bytes(const Pass& p) { const size_t d = (size_t)1 << p.k; return d * d * 8; }
-void mfma_encode(const Pass& p, const double* mat, unsigned char* dst) {
-  const size_t d = (size_t)1 << p.k;
-  float* f = reinterpret_cast<float*>(dst);
-  for (size_t i = 0; i < 2 * d * d; ++i) f[i] = (float)mat[i];
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8;
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+constexpr int kLayoutPair = 0;  // bit 0 not a target: float4 = (group 2j, group 2j+1) at one amplitude
+constexpr int kLayoutQ0 = 1;    // bit 0 is target 0: float4 = amplitudes (2t, 2t+1) of one group
+constexpr float kF16Scale = 16384.f;       // 2^14
+constexpr float kF16LoScale = 2048.f;      // 2^11
+
+// ---- host-side conversions (round to nearest even) ------------------------
+uint16_t host_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
 }
-void launch_mfma(const Pass&, int, void*, const unsigned char*, hipStream_t) {
-  throw DeviceError{hipErrorInvalidValue, "MFMA pass not built yet"};
+float host_bf16_to_f(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// ---- device-side conversions ----------------------------------------------
+__device__ __forceinline__ short dev_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+__device__ __forceinline__ float dev_bf16_f(short h) { return __uint_as_float((uint32_t)(uint16_t)h << 16); }
+
+struct MfmaArgs {
+  uint64_t tiles;                // 32-column tiles
+  uint64_t lowmask64[SV_MAX_K];  // element-space insertion masks, ascending
+  uint64_t stride[SV_MAX_K];     // element stride of local bit j (element = float4)
+  int kq;                        // number of element-space targets
+};
+
+template <int KQ>
+__device__ __forceinline__ uint64_t mf_base(uint64_t g, const MfmaArgs& a) {
+#pragma unroll
+  for (int j = 0; j < KQ; ++j) g = ((g & ~a.lowmask64[j]) << 1) | (g & a.lowmask64[j]);
+  return g;
+}
+
+template <int KQ>
+__device__ __forceinline__ uint64_t mf_off(int l, const MfmaArgs& a) {
+  uint64_t o = 0;
+#pragma unroll
+  for (int j = 0; j < KQ; ++j)
+    if ((l >> j) & 1) o += a.stride[j];
+  return o;
+}
+
+// PREC: SV_PREC_FP32_MFMA, SV_PREC_BF16X3 or SV_PREC_FP16X3.
+template <int K, int PREC, int LAYOUT>
+__global__ __launch_bounds__(256) void k_apply_mfma(float4* __restrict__ psi, const float4* __restrict__ Ag,
+                                                    const MfmaArgs a) {
+  extern __shared__ float4 lds4[];
+  constexpr int DK = 1 << K;                 // amplitudes per group
+  constexpr int MT = (2 * DK) / 32;          // 32-row output tiles
+  constexpr bool SPLIT = PREC != SV_PREC_FP32_MFMA;
+  constexpr int KS = SPLIT ? (2 * DK) / 16 : DK;   // k-steps
+  constexpr int FRAG_BYTES = SPLIT ? MT * KS * 2 * 64 * 16 : MT * KS * 64 * 4;
+  constexpr int KQ = LAYOUT == kLayoutPair ? K : K - 1;  // element-space targets
+  constexpr int COLS = LAYOUT == kLayoutPair ? 2 : 1;    // column tiles per lane
+  const int tid = threadIdx.x;
+  for (int i = tid; i < FRAG_BYTES / 16; i += 256) lds4[i] = Ag[i];
+  __syncthreads();
+  const int lane = tid & 63, h = lane >> 5, j = lane & 31;
+  const uint64_t wstride = (uint64_t)gridDim.x * 4;
+  for (uint64_t wt = (uint64_t)blockIdx.x * 4 + (tid >> 6); wt < a.tiles; wt += wstride) {
+    const uint64_t base = mf_base<KQ>(wt * 32 + j, a);
+    if constexpr (!SPLIT) {
+      // ---- FP32: k-step s is amplitude s; this lane supplies part h ----
+      float b[COLS][KS];
+      if constexpr (LAYOUT == kLayoutPair) {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const float4 f = psi[base + mf_off<KQ>(s, a)];
+          b[0][s] = h ? f.y : f.x;
+          b[1][s] = h ? f.w : f.z;
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < KS / 2; ++t) {
+          const float4 f = psi[base + mf_off<KQ>(t, a)];
+          b[0][2 * t] = h ? f.y : f.x;
+          b[0][2 * t + 1] = h ? f.w : f.z;
+        }
+      }
+      const float* A = reinterpret_cast<const float*>(lds4);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        f32x16 acc[COLS];
+#pragma unroll
+        for (int c = 0; c < COLS; ++c)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) acc[c][v] = 0.f;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const float av = A[(mt * KS + s) * 64 + lane];
+#pragma unroll
+          for (int c = 0; c < COLS; ++c) acc[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b[c][s], acc[c], 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = 16 * mt + 4 * q + 2 * h;  // rows 2r, 2r+1, 2r+2, 2r+3
+          if constexpr (LAYOUT == kLayoutPair) {
+            psi[base + mf_off<KQ>(r, a)] = make_float4(acc[0][4 * q], acc[0][4 * q + 1], acc[1][4 * q], acc[1][4 * q + 1]);
+            psi[base + mf_off<KQ>(r + 1, a)] =
+                make_float4(acc[0][4 * q + 2], acc[0][4 * q + 3], acc[1][4 * q + 2], acc[1][4 * q + 3]);
+          } else {
+            psi[base + mf_off<KQ>(r >> 1, a)] =
+                make_float4(acc[0][4 * q], acc[0][4 * q + 1], acc[0][4 * q + 2], acc[0][4 * q + 3]);
+          }
+        }
+      }
+    } else {
+      // ---- split precision: k-step s covers amplitudes 8s .. 8s+7; this
+      //      lane supplies amplitudes 8s + 4h .. 8s + 4h + 3 (re, im each) ----
+      using frag_t = typename std::conditional<PREC == SV_PREC_BF16X3, bf16x8, f16x8>::type;
+      frag_t bhi[COLS][KS], blo[COLS][KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        float x[COLS][8];
+        if constexpr (LAYOUT == kLayoutPair) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float4 f = psi[base + mf_off<KQ>(8 * s + 4 * h + q, a)];
+            x[0][2 * q] = f.x;
+            x[0][2 * q + 1] = f.y;
+            x[1][2 * q] = f.z;
+            x[1][2 * q + 1] = f.w;
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const float4 f = psi[base + mf_off<KQ>(4 * s + 2 * h + q, a)];
+            x[0][4 * q] = f.x;
+            x[0][4 * q + 1] = f.y;
+            x[0][4 * q + 2] = f.z;
+            x[0][4 * q + 3] = f.w;
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < COLS; ++c)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            if constexpr (PREC == SV_PREC_BF16X3) {
+              const short hi = dev_bf16(x[c][e]);
+              bhi[c][s][e] = hi;
+              blo[c][s][e] = dev_bf16(x[c][e] - dev_bf16_f(hi));
+            } else {
+              const float xs = x[c][e] * kF16Scale;
+              const _Float16 hi = (_Float16)xs;
+              bhi[c][s][e] = hi;
+              blo[c][s][e] = (_Float16)((xs - (float)hi) * kF16LoScale);
+            }
+          }
+      }
+      const frag_t* A = reinterpret_cast<const frag_t*>(lds4);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        f32x16 acc[COLS], cor[COLS];
+#pragma unroll
+        for (int c = 0; c < COLS; ++c)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) acc[c][v] = cor[c][v] = 0.f;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const frag_t ahi = A[((mt * KS + s) * 2 + 0) * 64 + lane];
+          const frag_t alo = A[((mt * KS + s) * 2 + 1) * 64 + lane];
+#pragma unroll
+          for (int c = 0; c < COLS; ++c) {
+            if constexpr (PREC == SV_PREC_BF16X3) {
+              acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi[c][s], acc[c], 0, 0, 0);
+              acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo[c][s], acc[c], 0, 0, 0);
+              acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi[c][s], acc[c], 0, 0, 0);
+            } else {
+              acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, bhi[c][s], acc[c], 0, 0, 0);
+              cor[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, blo[c][s], cor[c], 0, 0, 0);
+              cor[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(alo, bhi[c][s], cor[c], 0, 0, 0);
+            }
+          }
+        }
+        if constexpr (PREC == SV_PREC_FP16X3) {
+#pragma unroll
+          for (int c = 0; c < COLS; ++c)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[c][v] = (acc[c][v] + cor[c][v] * (1.f / kF16LoScale)) * (1.f / kF16Scale);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = 16 * mt + 4 * q + 2 * h;
+          if constexpr (LAYOUT == kLayoutPair) {
+            psi[base + mf_off<KQ>(r, a)] = make_float4(acc[0][4 * q], acc[0][4 * q + 1], acc[1][4 * q], acc[1][4 * q + 1]);
+            psi[base + mf_off<KQ>(r + 1, a)] =
+                make_float4(acc[0][4 * q + 2], acc[0][4 * q + 3], acc[1][4 * q + 2], acc[1][4 * q + 3]);
+          } else {
+            psi[base + mf_off<KQ>(r >> 1, a)] =
+                make_float4(acc[0][4 * q], acc[0][4 * q + 1], acc[0][4 * q + 2], acc[0][4 * q + 3]);
+          }
+        }
+      }
+    }
+  }
+}
+
+size_t frag_bytes(int k, int prec) {
+  const int dk = 1 << k, mt = 2 * dk / 32;
+  if (prec == SV_PREC_FP32_MFMA) return (size_t)mt * dk * 64 * 4;
+  return (size_t)mt * (2 * dk / 16) * 2 * 64 * 16;
+}
+
+// Entry (row, col) of the real 4M-form matrix with (amplitude, re/im) order.
+inline double a4m(const double* mat, int dk, int row, int col) {
+  const int r = row >> 1, pr = row & 1, c = col >> 1, pc = col & 1;
+  const double ur = mat[2 * (r * dk + c)], ui = mat[2 * (r * dk + c) + 1];
+  if (pr == 0) return pc == 0 ? ur : -ui;
+  return pc == 0 ? ui : ur;
+}
+
+template <int K, int PREC, int LAYOUT>
+void launch_t(const MfmaArgs& a, void* psi, const unsigned char* data, hipStream_t st) {
+  const size_t lds = frag_bytes(K, PREC);
+  uint64_t blocks = (a.tiles + 3) / 4;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL((k_apply_mfma<K, PREC, LAYOUT>), dim3((unsigned)blocks), dim3(256), lds, st, (float4*)psi,
+                     (const float4*)data, a);
+}
+
+template <int PREC, int LAYOUT>
+void launch_k(int k, const MfmaArgs& a, void* psi, const unsigned char* data, hipStream_t st) {
+  switch (k) {
+    case 4: return launch_t<4, PREC, LAYOUT>(a, psi, data, st);
+    case 5: return launch_t<5, PREC, LAYOUT>(a, psi, data, st);
+    case 6: return launch_t<6, PREC, LAYOUT>(a, psi, data, st);
+    default: throw DeviceError{hipErrorInvalidValue, "k_apply_mfma: k must be 4..6"};
+  }
+}
+
+}  // namespace
+
+bool mfma_supported(int k, int precision) {
+  return k >= 4 && k <= 6 &&
+         (precision == SV_PREC_FP32_MFMA || precision == SV_PREC_BF16X3 || precision == SV_PREC_FP16X3);
+}
+
+size_t mfma_data_bytes(const Pass& p) { return frag_bytes(p.k, p.precision); }
+
+// A' in fragment order.  FP32: [mt][s][lane] with lane (h, i) holding
+// A'[32 mt + i][2 s + h].  Split: [mt][s][part][lane][e] with lane (h, i)
+// holding A'[32 mt + i][16 s + 8 h + e]; part 0 = hi, part 1 = lo.
+void mfma_encode(const Pass& p, const double* mat, unsigned char* dst) {
+  const int dk = 1 << p.k, mt_n = 2 * dk / 32;
+  if (p.precision == SV_PREC_FP32_MFMA) {
+    float* f = reinterpret_cast<float*>(dst);
+    for (int mt = 0; mt < mt_n; ++mt)
+      for (int s = 0; s < dk; ++s)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int h = lane >> 5, i = lane & 31;
+          f[(mt * dk + s) * 64 + lane] = (float)a4m(mat, dk, 32 * mt + i, 2 * s + h);
+        }
+    return;
+  }
+  const int ks_n = 2 * dk / 16;
+  uint16_t* o = reinterpret_cast<uint16_t*>(dst);
+  for (int mt = 0; mt < mt_n; ++mt)
+    for (int s = 0; s < ks_n; ++s)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int e = 0; e < 8; ++e) {
+          const int h = lane >> 5, i = lane & 31;
+          const double v = a4m(mat, dk, 32 * mt + i, 16 * s + 8 * h + e);
+          uint16_t hi, lo;
+          if (p.precision == SV_PREC_BF16X3) {
+            hi = host_bf16((float)v);
+            lo = host_bf16((float)(v - (double)host_bf16_to_f(hi)));
+          } else {
+            const _Float16 fh = (_Float16)v;
+            const _Float16 fl = (_Float16)((v - (double)(float)fh) * (double)kF16LoScale);
+            std::memcpy(&hi, &fh, 2);
+            std::memcpy(&lo, &fl, 2);
+          }
+          const size_t base = (((size_t)(mt * ks_n + s) * 2) * 64 + lane) * 8 + e;
+          o[base] = hi;
+          o[base + (size_t)64 * 8] = lo;
+        }
+}
+
+void launch_mfma(const Pass& p, int n, void* psi, const unsigned char* data, hipStream_t st) {
+  MfmaArgs a{};
+  int pos[SV_MAX_K];
+  int layout;
+  if (p.s[0] == 0) {
+    layout = kLayoutQ0;
+    a.kq = p.k - 1;
+    for (int j = 0; j < a.kq; ++j) pos[j] = p.s[j + 1] - 1;
+    a.tiles = ((uint64_t)1 << (n - p.k)) / 32;
+  } else {
+    layout = kLayoutPair;
+    a.kq = p.k;
+    for (int j = 0; j < a.kq; ++j) pos[j] = p.s[j] - 1;
+    a.tiles = ((uint64_t)1 << (n - 1 - p.k)) / 32;
+  }
+  for (int j = 0; j < a.kq; ++j) {
+    a.lowmask64[j] = ((uint64_t)1 << pos[j]) - 1;
+    a.stride[j] = (uint64_t)1 << pos[j];
+  }
+  if (a.tiles == 0) throw DeviceError{hipErrorInvalidValue, "k_apply_mfma: state too small for a 32-group tile"};
+  const bool pair = layout == kLayoutPair;
+  switch (p.precision) {
+    case SV_PREC_FP32_MFMA:
+      pair ? launch_k<SV_PREC_FP32_MFMA, kLayoutPair>(p.k, a, psi, data, st)
+           : launch_k<SV_PREC_FP32_MFMA, kLayoutQ0>(p.k, a, psi, data, st);
+      break;
+    case SV_PREC_BF16X3:
+      pair ? launch_k<SV_PREC_BF16X3, kLayoutPair>(p.k, a, psi, data, st)
+           : launch_k<SV_PREC_BF16X3, kLayoutQ0>(p.k, a, psi, data, st);
+      break;
+    case SV_PREC_FP16X3:
+      pair ? launch_k<SV_PREC_FP16X3, kLayoutPair>(p.k, a, psi, data, st)
+           : launch_k<SV_PREC_FP16X3, kLayoutQ0>(p.k, a, psi, data, st);
+      break;
+    default:
+      throw DeviceError{hipErrorInvalidValue, "k_apply_mfma: precision"};
+  }
 }
 
 }  // namespace sv

@@ -72,6 +72,7 @@ void normalise_gate(int k, const int32_t* qubits, const double* mat, int* sorted
 int choose_variant(int n, int k, const int* s, int precision, int requested);
 Shape tuned_shape(int variant, int n, int k, const int* s, int precision);
 int lds_split(int tile_bits, int k, const int* s, int* m_out);
+int lds_tile_bits_for(int n, int want);
 
 // Fusion (fuse.cpp).
 struct FusedGate {

@@ -206,3 +206,56 @@ def test_many_small_gates_wrap_the_arena():
         check(st.read(), oracle.apply_circuit(n, gates), max_abs=1e-4, infid=1e-5)
     finally:
         st.free()
+
+
+# --------------------------------------------------------------------------
+# Matrix-core passes (k >= 4): FP32 MFMA and split BF16/FP16 (hi + lo)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["fp32_mfma", "bf16x3", "fp16x3"])
+@pytest.mark.parametrize("k", [4, 5, 6])
+@pytest.mark.parametrize("tname", list(TARGET_SETS))
+def test_mfma_single_gate(prec, k, tname):
+    n = 14
+    qs = TARGET_SETS[tname](n, k)
+    rng = np.random.Generator(np.random.PCG64(k * 1000 + len(tname) + len(prec)))
+    gates = random_state_circuit(n, k) + [C.Gate(qs, C.haar_unitary(k, rng))]
+    say("mfma single gate", prec, k, tname, qs)
+    got = run_gpu(n, gates, fusion="none", precision=prec, variant="mfma")
+    check(got, oracle.apply_circuit(n, gates))
+
+
+@pytest.mark.parametrize("prec", ["fp32_mfma", "bf16x3", "fp16x3"])
+@pytest.mark.parametrize("max_k", [4, 5, 6])
+def test_grid_fused_mfma(prec, max_k):
+    n = 20
+    gates = C.grid_circuit(4, 5, 14, seed=2)
+    ref = oracle.apply_circuit(n, gates)
+    say("grid fused mfma", prec, max_k)
+    r = check(run_gpu(n, gates, max_k=max_k, fusion="greedy", precision=prec), ref)
+    say(r)
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3"])
+def test_qft_like_split_precision_closed_form(prec):
+    """Config-3 analogue: QFT-like circuit from a seeded basis state, fused to
+    k = 5, split-precision matrix cores; checked against the closed form."""
+    n = 24
+    x = C.qft_input_basis(n, 11)
+    sv = _sv()
+    st = sv.State(n)
+    try:
+        st.set_basis(x)
+        st.apply_circuit(C.qft_like_circuit(n), max_k=5, precision=prec)
+        r = check(st.read(), oracle.qft_like_amplitudes(n, x, np.arange(1 << n)))
+        say(prec, r)
+        assert abs(st.norm() - 1) < 1e-5
+    finally:
+        st.free()
+
+
+def test_mfma_small_state_falls_back():
+    """States too small for a 32-group tile run the VALU kernel instead."""
+    n = 9
+    rng = np.random.Generator(np.random.PCG64(8))
+    gates = random_state_circuit(n, 1) + [C.Gate((0, 2, 4, 6, 8), C.haar_unitary(5, rng))]
+    check(run_gpu(n, gates, fusion="none", precision="bf16x3", variant="mfma"), oracle.apply_circuit(n, gates))

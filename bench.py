@@ -85,9 +85,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="grid34")
-    ap.add_argument("--max-k", type=int, default=4)
+    ap.add_argument("--max-k", type=int, default=6)
     ap.add_argument("--fusion", default="greedy")
-    ap.add_argument("--precision", default="fp32_valu")
+    ap.add_argument("--precision", default="bf16x3")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (untuned defaults)")
+    ap.add_argument("--tune-qubits", type=int, default=30)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain unfused FP32 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -102,6 +104,16 @@ def main():
 
     n, gates, desc = workload(args.workload)
     log("workload:", desc, "gates:", len(gates))
+    tuned = False
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        scratch = sv.State(min(args.tune_qubits, n))
+        sv.sv_autotune(scratch.h, 0)
+        scratch.free()
+        del scratch
+        torch.cuda.empty_cache()
+        tuned = True
+        log("autotune: %.1f s" % (time.perf_counter() - t0))
     sample = 1 << 20
     st = sv.State(n)
     opts = dict(max_k=args.max_k, fusion=args.fusion, precision=args.precision, timing=True)
@@ -139,7 +151,7 @@ def main():
 
     extra = {
         "passes_per_step": int(sum(passes) / args.steps),
-        "fused_max_k": args.max_k, "fusion": args.fusion, "precision": args.precision,
+        "fused_max_k": args.max_k, "fusion": args.fusion, "precision": args.precision, "autotuned": tuned,
         "alg_hbm_GBps_passes": hbm_gbps_alg,
         "gpu_s_per_step": agg["gpu_s"] / args.steps,
         "fuse_s_per_step": agg["fuse_s"] / args.steps,

@@ -1,0 +1,117 @@
+"""Timing corpus and GPU training of the fusion cost model.
+
+The simulator times its own passes: for sampled (k, target qubits, n,
+precision) one gate is applied through sv_apply_circuit with per-pass HIP
+event timing, and the target is ln(pass seconds * 1e9 / 2^n).  Target sets
+come half from uniform random subsets and half from the blocks that greedy
+fusion builds on random grid circuits (the masks the partition search will
+actually score).  Training runs the library's MLP kernels (sv_mlp_*); the
+trained network is installed for SV_FUSE_LEARNED and can be saved.
+"""
+from __future__ import annotations
+
+import math
+import time
+from typing import Dict, Sequence
+
+import numpy as np
+
+from . import sv
+
+PRECISIONS = ("fp32_valu", "bf16x3", "fp16x3", "fp32_mfma")
+
+
+def _grid_like_blocks(n: int, rng: np.random.Generator):
+    """Qubit sets of greedily fused blocks of a random grid-like circuit on n qubits."""
+    import circuits as C
+    rows = 2 if n % 2 == 0 else 1
+    cols = n // rows
+    gates = C.grid_circuit(rows, cols, 6, seed=int(rng.integers(1 << 30)))
+    if rows * cols < n:
+        gates = [C.Gate(tuple(q + 1 for q in g.qubits), g.matrix) for g in gates]
+    K = int(rng.integers(2, 7))
+    fused, _ = sv.sv_fuse(gates, n, sv.make_opts(max_k=K))
+    return [f.qubits for f in fused]
+
+
+def collect_corpus(samples: int = 1200, ns: Sequence[int] = (20, 24, 28, 30),
+                   precisions: Sequence[str] = PRECISIONS, seed: int = 0, repeats: int = 2,
+                   log=None) -> Dict[str, np.ndarray]:
+    """Time `samples` single passes; returns X [samples, 40], y [samples] and the raw fields."""
+    import circuits as C
+    rng = np.random.Generator(np.random.PCG64(seed))
+    per_n = [samples // len(ns) + (1 if i < samples % len(ns) else 0) for i in range(len(ns))]
+    X, y, ks, masks, nn, precs, secs = [], [], [], [], [], [], []
+    t0 = time.perf_counter()
+    for n, count in zip(ns, per_n):
+        st = sv.State(n)
+        pool = []
+        try:
+            for i in range(count):
+                if not pool:
+                    pool = _grid_like_blocks(n, rng)
+                if i % 2 == 0:
+                    k = int(rng.integers(1, 7))
+                    qs = tuple(int(q) for q in rng.permutation(n)[:k])
+                else:
+                    qs = pool.pop(int(rng.integers(len(pool))))
+                    k = len(qs)
+                prec = precisions[int(rng.integers(len(precisions)))]
+                g = [C.Gate(qs, C.haar_unitary(k, rng))]
+                best = math.inf
+                for _ in range(repeats):
+                    s = st.apply_circuit(g, fusion="none", precision=prec, timing=True)
+                    best = min(best, s["gpu_s"])
+                pid = sv.PRECISIONS[prec]
+                X.append(sv.sv_cost_features(k, qs, n, pid))
+                y.append(math.log(best * 1e9 / (1 << n)))
+                ks.append(k)
+                masks.append(sum(1 << q for q in qs))
+                nn.append(n)
+                precs.append(pid)
+                secs.append(best)
+                if (i + 1) % 200 == 0 and log:
+                    log("corpus n=%d: %d/%d (%.1f s)" % (n, i + 1, count, time.perf_counter() - t0))
+                if (i + 1) % 64 == 0:
+                    st.set_basis(0)  # keep the state normalised and finite
+        finally:
+            st.free()
+    return {"X": np.array(X, dtype=np.float32), "y": np.array(y, dtype=np.float32),
+            "k": np.array(ks), "mask": np.array(masks, dtype=np.uint64), "n": np.array(nn),
+            "precision": np.array(precs), "seconds": np.array(secs)}
+
+
+def spearman(a, b) -> float:
+    ra = np.argsort(np.argsort(a))
+    rb = np.argsort(np.argsort(b))
+    return float(np.corrcoef(ra, rb)[0, 1])
+
+
+def train_cost_model(corpus: Dict[str, np.ndarray], epochs: int = 3000, lr: float = 3e-3, seed: int = 0,
+                     holdout: float = 0.2, install: bool = True, save_path: str | None = None) -> dict:
+    """Train on the GPU, report held-out error, install as the fusion cost model."""
+    import torch
+    X, y = corpus["X"], corpus["y"]
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    idx = rng.permutation(len(y))
+    n_test = int(len(y) * holdout)
+    te, tr = idx[:n_test], idx[n_test:]
+    m = sv.Mlp(seed=seed)
+    try:
+        xd = torch.tensor(X[tr], device="cuda")
+        yd = torch.tensor(y[tr], device="cuda")
+        t0 = time.perf_counter()
+        loss = m.train(xd, yd, epochs=epochs, lr=lr)
+        train_s = time.perf_counter() - t0
+        out = {"train_mse": loss, "train_s": train_s, "epochs": epochs, "samples": int(len(tr))}
+        if n_test:
+            pred = m.forward(torch.tensor(X[te], device="cuda"))
+            out["test_rmse"] = float(np.sqrt(np.mean((pred - y[te]) ** 2)))
+            out["test_spearman"] = spearman(pred, y[te])
+        if install:
+            m.install()
+            if save_path:
+                sv.sv_cost_model_save(save_path)
+        return out
+    finally:
+        m.free()

@@ -258,7 +258,7 @@ int sv_alloc(int n_qubits, int dtype, void* dev_buf, size_t buf_bytes, void* hip
   SV_HIP(hipHostMalloc(&s->norm_host, sizeof(double), hipHostMallocDefault));
   SV_HIP(hipEventCreate(&s->ev0));
   SV_HIP(hipEventCreate(&s->ev1));
-  arena_reserve(s, kArenaInit);
+  // the matrix arena is allocated on the first gate upload
   launch_init_basis(s->psi, s->n, 0, s->stream);
   *out = s;
   return SV_OK;

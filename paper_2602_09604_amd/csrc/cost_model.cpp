@@ -1,34 +1,217 @@
-// Learned fusion cost model: features, host inference, partition search.
+// Learned fusion: the installed MLP predicts the time of one pass from
+// (k, target mask, n, precision); the partition search scores candidate
+// partitions with it and keeps the cheapest.  Without a model, fusion falls
+// back to greedy max-k.
+//
+// Prediction target: ln(pass seconds * 1e9 / 2^n), i.e. the log of the pass
+// time per amplitude in nanoseconds, which stays comparable across state
+// sizes.  A pass costs exp(pred) * 2^n ns plus a fixed launch overhead.
+//
+// Candidates (Sec. IV-D: the best fusion size depends on circuit and
+// platform, Sec. VII-B picks it by measurement):
+//   - greedy max-k partitions for k = 1 .. max_k;
+//   - cost-aware greedy: a gate that would grow a block joins only when the
+//     predicted cost of the larger block does not exceed the smaller block's
+//     cost plus alpha times the cost of running the gate as a pass of its own,
+//     for several alpha.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <functional>
+#include <mutex>
+#include <unordered_map>
+
 #include "sv_internal.h"
 
 namespace sv {
 
+void greedy_partition(const sv_gate* g, size_t n, int max_k, std::vector<std::vector<int>>& blocks);
+void greedy_partition_cost(const sv_gate* g, size_t n, int max_k,
+                           const std::function<bool(uint64_t, uint64_t, uint64_t)>& accept,
+                           std::vector<std::vector<int>>& blocks);
+void fuse_blocks(const sv_gate* g, size_t n, const std::vector<std::vector<int>>& blocks,
+                 std::vector<FusedGate>& out, std::vector<int32_t>& block_of);
+
+namespace {
+
+constexpr int F = SV_COST_FEATURES;
+constexpr double kLaunchOverheadNs = 4000.0;
+
+std::mutex g_mu;
+std::vector<float> g_params;
+int g_width = 0;
+
+int num_params(int w) { return w * F + w + w * w + w + w + 1; }
+
+double forward(const std::vector<float>& P, int W, const float* x) {
+  const float* W1 = P.data();
+  const float* b1 = W1 + W * F;
+  const float* W2 = b1 + W;
+  const float* b2 = W2 + W * W;
+  const float* W3 = b2 + W;
+  const float* b3 = W3 + W;
+  std::vector<double> h1(W), h2(W);
+  for (int j = 0; j < W; ++j) {
+    double a = b1[j];
+    for (int f = 0; f < F; ++f) a += (double)W1[j * F + f] * x[f];
+    h1[j] = a > 0 ? a : 0;
+  }
+  for (int j = 0; j < W; ++j) {
+    double a = b2[j];
+    for (int q = 0; q < W; ++q) a += (double)W2[j * W + q] * h1[q];
+    h2[j] = a > 0 ? a : 0;
+  }
+  double y = b3[0];
+  for (int q = 0; q < W; ++q) y += (double)W3[q] * h2[q];
+  return y;
+}
+
+}  // namespace
+
 void cost_features(int k, const int* qubits, int n, int precision, float* out) {
-  for (int i = 0; i < SV_COST_FEATURES; ++i) out[i] = 0.f;
+  for (int i = 0; i < F; ++i) out[i] = 0.f;
   out[0] = k / 6.0f;
   out[1] = n / 34.0f;
   for (int j = 0; j < k; ++j)
-    if (qubits[j] < 34) out[2 + qubits[j]] = 1.f;
+    if (qubits[j] >= 0 && qubits[j] < 34) out[2 + qubits[j]] = 1.f;
   if (precision >= 0 && precision < 4) out[36 + precision] = 1.f;
 }
-bool cost_model_ready() { return false; }
-double cost_model_predict_log(int, const int*, int, int) { return 0.0; }
-bool fuse_learned(const sv_gate*, size_t, int, int, int, std::vector<FusedGate>&, std::vector<int32_t>&) {
-  return false;
+
+void cost_model_set(const std::vector<float>& params, int width) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_params = params;
+  g_width = width;
+}
+
+bool cost_model_ready() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_width > 0 && (int)g_params.size() == num_params(g_width);
+}
+
+double cost_model_predict_log(int k, const int* qubits, int n, int precision) {
+  float x[F];
+  cost_features(k, qubits, n, precision, x);
+  std::lock_guard<std::mutex> lk(g_mu);
+  return forward(g_params, g_width, x);
+}
+
+bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int precision, std::vector<FusedGate>& out,
+                  std::vector<int32_t>& block_of) {
+  if (!cost_model_ready()) return false;
+  std::unordered_map<uint64_t, double> cache;
+  const double amps = std::ldexp(1.0, n_qubits);
+  auto pass_ns = [&](uint64_t mask) {
+    auto it = cache.find(mask);
+    if (it != cache.end()) return it->second;
+    int q[64], k = 0;
+    for (int b = 0; b < 64 && k < SV_MAX_K; ++b)
+      if ((mask >> b) & 1) q[k++] = b;
+    const double t = std::exp(cost_model_predict_log(k, q, n_qubits, precision)) * amps + kLaunchOverheadNs;
+    cache[mask] = t;
+    return t;
+  };
+  auto mask_of = [&](int i) {
+    uint64_t m = 0;
+    for (int j = 0; j < g[i].k; ++j) m |= (uint64_t)1 << g[i].qubits[j];
+    return m;
+  };
+  auto total = [&](const std::vector<std::vector<int>>& blocks) {
+    double t = 0;
+    for (auto& b : blocks) {
+      uint64_t m = 0;
+      for (int i : b) m |= mask_of(i);
+      t += pass_ns(m);
+    }
+    return t;
+  };
+  std::vector<std::vector<int>> best, cand;
+  double best_t = 1e300;
+  for (int K = 1; K <= max_k; ++K) {
+    greedy_partition(g, n, K, cand);
+    const double t = total(cand);
+    if (t < best_t) {
+      best_t = t;
+      best = cand;
+    }
+  }
+  for (double alpha : {0.25, 0.5, 1.0}) {
+    greedy_partition_cost(
+        g, n, max_k,
+        [&](uint64_t S, uint64_t S2, uint64_t qh) {
+          if (S2 == S) return true;  // vertical fusion never costs a pass
+          return pass_ns(S2) - pass_ns(S) <= alpha * pass_ns(qh);
+        },
+        cand);
+    const double t = total(cand);
+    if (t < best_t) {
+      best_t = t;
+      best = cand;
+    }
+  }
+  fuse_blocks(g, n, best, out, block_of);
+  return true;
 }
 
 }  // namespace sv
 
+using namespace sv;
+
+// File: "SVCM" magic, u32 version 1, u32 width, u32 features, u32 count,
+// then count little-endian float32 parameters.
 extern "C" {
-int sv_cost_model_install(sv_mlp*) { return sv::fail(SV_EUNSUPPORTED, "cost model not built yet"); }
-int sv_cost_model_save(const char*) { return sv::fail(SV_EUNSUPPORTED, "cost model not built yet"); }
-int sv_cost_model_load(const char*) { return sv::fail(SV_EUNSUPPORTED, "cost model not built yet"); }
-int sv_cost_model_predict(int, const int32_t*, int, int, double*) {
-  return sv::fail(SV_EUNSUPPORTED, "cost model not built yet");
+
+int sv_cost_model_save(const char* path) {
+  if (!path) return fail(SV_EINVAL, "path is NULL");
+  std::vector<float> p;
+  int w;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    p = g_params;
+    w = g_width;
+  }
+  if (w == 0) return fail(SV_EINVAL, "no cost model installed");
+  std::ofstream f(path, std::ios::binary);
+  if (!f) return fail(SV_EINVAL, std::string("cannot write ") + path);
+  const uint32_t hdr[5] = {0x4D435653u, 1u, (uint32_t)w, (uint32_t)F, (uint32_t)p.size()};
+  f.write((const char*)hdr, sizeof(hdr));
+  f.write((const char*)p.data(), sizeof(float) * p.size());
+  return f ? SV_OK : fail(SV_EINVAL, "write failed");
 }
-int sv_cost_features(int k, const int32_t* qubits, int n_qubits, int precision, float* out) {
-  if (!qubits || !out || k < 1 || k > SV_MAX_K) return sv::fail(SV_EINVAL, "bad arguments");
-  sv::cost_features(k, qubits, n_qubits, precision, out);
+
+int sv_cost_model_load(const char* path) {
+  if (!path) return fail(SV_EINVAL, "path is NULL");
+  std::ifstream f(path, std::ios::binary);
+  if (!f) return fail(SV_EINVAL, std::string("cannot read ") + path);
+  uint32_t hdr[5];
+  if (!f.read((char*)hdr, sizeof(hdr))) return fail(SV_EINVAL, "truncated cost model file");
+  if (hdr[0] != 0x4D435653u || hdr[1] != 1u) return fail(SV_EINVAL, "not a cost model file");
+  if (hdr[2] != 64 || hdr[3] != (uint32_t)F || hdr[4] != (uint32_t)num_params((int)hdr[2]))
+    return fail(SV_EINVAL, "cost model shape mismatch");
+  std::vector<float> p(hdr[4]);
+  if (!f.read((char*)p.data(), sizeof(float) * p.size())) return fail(SV_EINVAL, "truncated cost model file");
+  for (float v : p)
+    if (!std::isfinite(v)) return fail(SV_EINVAL, "non-finite parameter");
+  cost_model_set(p, (int)hdr[2]);
   return SV_OK;
 }
+
+int sv_cost_model_predict(int k, const int32_t* qubits, int n_qubits, int precision, double* out) {
+  if (!qubits || !out || k < 1 || k > SV_MAX_K || n_qubits < 1 || n_qubits > SV_MAX_QUBITS)
+    return fail(SV_EINVAL, "bad arguments");
+  if (!cost_model_ready()) return fail(SV_EINVAL, "no cost model installed");
+  int q[SV_MAX_K];
+  for (int j = 0; j < k; ++j) q[j] = qubits[j];
+  *out = cost_model_predict_log(k, q, n_qubits, precision);
+  return SV_OK;
 }
+
+int sv_cost_features(int k, const int32_t* qubits, int n_qubits, int precision, float* out) {
+  if (!qubits || !out || k < 1 || k > SV_MAX_K) return fail(SV_EINVAL, "bad arguments");
+  int q[SV_MAX_K];
+  for (int j = 0; j < k; ++j) q[j] = qubits[j];
+  cost_features(k, q, n_qubits, precision, out);
+  return SV_OK;
+}
+
+}  // extern "C"

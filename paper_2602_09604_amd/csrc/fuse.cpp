@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <complex>
 #include <cstring>
+#include <functional>
 
 #include "sv_internal.h"
 
@@ -124,8 +125,13 @@ void fuse_none(const sv_gate* g, size_t n, std::vector<FusedGate>& out, std::vec
   }
 }
 
-// Greedy partition into member lists (indices into g), blocks in emission order.
-void greedy_partition(const sv_gate* g, size_t n, int max_k, std::vector<std::vector<int>>& blocks) {
+// Greedy partition into member lists (indices into g), blocks in emission
+// order.  accept(S, S_new, q) may veto a join that passes the size and
+// blocking rules (S = block qubits now, S_new = after the join, q = the
+// gate's qubits); a vetoed gate blocks its qubits like any other skipped gate.
+void greedy_partition_cost(const sv_gate* g, size_t n, int max_k,
+                           const std::function<bool(uint64_t, uint64_t, uint64_t)>& accept,
+                           std::vector<std::vector<int>>& blocks) {
   blocks.clear();
   std::vector<uint64_t> masks(n);
   for (size_t i = 0; i < n; ++i) masks[i] = qmask(g[i]);
@@ -138,8 +144,9 @@ void greedy_partition(const sv_gate* g, size_t n, int max_k, std::vector<std::ve
     for (size_t h = seed + 1; h < n; ++h) {
       if (consumed[h]) continue;
       const uint64_t qh = masks[h];
-      if ((qh & blocked) == 0 && __builtin_popcountll(S | qh) <= max_k) {
-        S |= qh;
+      const uint64_t S2 = S | qh;
+      if ((qh & blocked) == 0 && __builtin_popcountll(S2) <= max_k && (!accept || accept(S, S2, qh))) {
+        S = S2;
         members.push_back((int)h);
         consumed[h] = 1;
       } else {
@@ -150,6 +157,10 @@ void greedy_partition(const sv_gate* g, size_t n, int max_k, std::vector<std::ve
     }
     blocks.push_back(std::move(members));
   }
+}
+
+void greedy_partition(const sv_gate* g, size_t n, int max_k, std::vector<std::vector<int>>& blocks) {
+  greedy_partition_cost(g, n, max_k, nullptr, blocks);
 }
 
 void fuse_blocks(const sv_gate* g, size_t n, const std::vector<std::vector<int>>& blocks,

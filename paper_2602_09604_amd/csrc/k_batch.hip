@@ -1,7 +1,393 @@
-// Batched persistent kernel for many small circuits.
-#include "sv_internal.h"
+// Batched simulation of many independent small circuits.
+//
+// Two kernels, both launched inside one captured hipGraph:
+//   k_batch_lds    one workgroup per circuit whose state fits in LDS: load the
+//                  state once, apply every fused pass of the circuit from LDS,
+//                  store once.  HBM traffic is one read and one write per
+//                  circuit instead of one per pass.
+//   k_batch_level  every larger circuit advances one fused pass per launch;
+//                  a launch covers pass L of all circuits that have one, each
+//                  workgroup owning 256 lane work items of one circuit, so the
+//                  grid is filled by the whole batch instead of by one state.
+//                  The kernel boundary is the barrier between dependent passes
+//                  of a circuit (it also makes every XCD's writes visible to
+//                  the next pass without spinning on device flags).
+// The LDS branch runs on a forked capture stream, so it overlaps the level
+// launches of the large circuits.  The LDS-resident size limit is chosen by
+// the autotuner.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <mutex>
 
-extern "C" int sv_batch_run(sv_state* const*, const sv_gate* const*, const size_t*, size_t, const sv_run_opts*,
-                            sv_run_stats*) {
-  return sv::fail(SV_EUNSUPPORTED, "batched kernel not built yet");
+#include "k_common.h"
+
+namespace sv {
+
+void* state_psi(sv_state* s);
+int state_n(sv_state* s);
+hipStream_t state_stream(sv_state* s);
+bool state_poisoned(sv_state* s);
+void state_poison(sv_state* s);
+
+namespace {
+using namespace kern;
+
+// One fused pass of one circuit, in element space (see k_apply_reg modes).
+struct BPass {
+  uint64_t items;             // lane work items
+  uint64_t lowmask[SV_MAX_K];
+  uint64_t stride[SV_MAX_K];
+  uint32_t mat;               // float2 index of the complex64 matrix
+  int mode, K;
+};
+
+struct BCirc {
+  float2* psi;
+  int n;
+  int pass0, npass;
+};
+
+template <int K, int MODE, typename PTR2, typename PTR4>
+__device__ __forceinline__ void apply_item(PTR2 psi2, PTR4 psi4, const float2* __restrict__ U, const BPass& p,
+                                           uint64_t g) {
+  constexpr int D = 1 << K;
+  uint64_t base = g;
+#pragma unroll
+  for (int j = 0; j < K; ++j) base = ((base & ~p.lowmask[j]) << 1) | (base & p.lowmask[j]);
+  if constexpr (MODE == 2) {
+    float2 v[D];
+#pragma unroll
+    for (int l = 0; l < D; ++l) v[l] = psi2[base + local_offset<K, uint64_t>(l, p.stride)];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int c = 0; c < D; ++c) cmac(acc, U[r * D + c], v[c]);
+      psi2[base + local_offset<K, uint64_t>(r, p.stride)] = acc;
+    }
+  } else {
+    float4 v[D];
+#pragma unroll
+    for (int l = 0; l < D; ++l) v[l] = psi4[base + local_offset<K, uint64_t>(l, p.stride)];
+#pragma unroll
+    for (int r = 0; r < D; ++r) psi4[base + local_offset<K, uint64_t>(r, p.stride)] = pair_row<K, MODE>(v, U, r);
+  }
+}
+
+// Dispatch on the pass shape (uniform across the workgroup).
+template <typename PTR2, typename PTR4>
+__device__ void apply_dispatch(PTR2 psi2, PTR4 psi4, const float2* __restrict__ U, const BPass& p, uint64_t g) {
+  switch (p.mode * 8 + p.K) {
+    case 0 * 8 + 1: apply_item<1, 0>(psi2, psi4, U, p, g); break;
+    case 0 * 8 + 2: apply_item<2, 0>(psi2, psi4, U, p, g); break;
+    case 0 * 8 + 3: apply_item<3, 0>(psi2, psi4, U, p, g); break;
+    case 0 * 8 + 4: apply_item<4, 0>(psi2, psi4, U, p, g); break;
+    case 0 * 8 + 5: apply_item<5, 0>(psi2, psi4, U, p, g); break;
+    case 1 * 8 + 0: apply_item<0, 1>(psi2, psi4, U, p, g); break;
+    case 1 * 8 + 1: apply_item<1, 1>(psi2, psi4, U, p, g); break;
+    case 1 * 8 + 2: apply_item<2, 1>(psi2, psi4, U, p, g); break;
+    case 1 * 8 + 3: apply_item<3, 1>(psi2, psi4, U, p, g); break;
+    case 1 * 8 + 4: apply_item<4, 1>(psi2, psi4, U, p, g); break;
+    case 1 * 8 + 5: apply_item<5, 1>(psi2, psi4, U, p, g); break;
+    case 2 * 8 + 6: apply_item<6, 2>(psi2, psi4, U, p, g); break;
+    default: break;  // shapes are checked on the host
+  }
+}
+
+// One workgroup per LDS-resident circuit (state of 2^n <= 2^13 amplitudes).
+__global__ __launch_bounds__(256) void k_batch_lds(const BCirc* __restrict__ circs, const int* __restrict__ which,
+                                                   const BPass* __restrict__ passes, const float2* __restrict__ mats) {
+  extern __shared__ float4 st4[];
+  float2* st2 = reinterpret_cast<float2*>(st4);
+  const BCirc c = circs[which[blockIdx.x]];
+  const int pairs = 1 << (c.n - 1);
+  float4* g4 = reinterpret_cast<float4*>(c.psi);
+  for (int i = threadIdx.x; i < pairs; i += 256) st4[i] = g4[i];
+  __syncthreads();
+  for (int pi = 0; pi < c.npass; ++pi) {
+    const BPass p = passes[c.pass0 + pi];
+    for (uint64_t g = threadIdx.x; g < p.items; g += 256) apply_dispatch(st2, st4, mats + p.mat, p, g);
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < pairs; i += 256) g4[i] = st4[i];
+}
+
+// Pass `level` of every circuit in `active` (count entries); first_block is
+// the prefix sum of workgroups per active circuit (count + 1 entries).
+__global__ __launch_bounds__(256) void k_batch_level(const BCirc* __restrict__ circs, const int* __restrict__ active,
+                                                     const uint64_t* __restrict__ first_block, int count, int level,
+                                                     const BPass* __restrict__ passes,
+                                                     const float2* __restrict__ mats) {
+  const uint64_t b = blockIdx.x;
+  int lo = 0, hi = count - 1;  // last entry with first_block <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first_block[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const BCirc c = circs[active[lo]];
+  const BPass p = passes[c.pass0 + level];
+  const uint64_t g = (b - first_block[lo]) * 256 + threadIdx.x;
+  if (g >= p.items) return;
+  apply_dispatch(c.psi, reinterpret_cast<float4*>(c.psi), mats + p.mat, p, g);
+}
+
+std::mutex g_batch_mu;
+int g_lds_max_n = 12;  // largest LDS-resident state (qubits); set by the autotuner
+
+void fill_pass(BPass& bp, int n, const FusedGate& f, uint32_t mat) {
+  int pos[SV_MAX_K];
+  if (f.q[0] == 0) {
+    bp.mode = 1;
+    bp.K = f.k - 1;
+    for (int j = 0; j < bp.K; ++j) pos[j] = f.q[j + 1] - 1;
+    bp.items = (uint64_t)1 << (n - 1 - bp.K);
+  } else if (f.k <= 5) {
+    bp.mode = 0;
+    bp.K = f.k;
+    for (int j = 0; j < bp.K; ++j) pos[j] = f.q[j] - 1;
+    bp.items = (uint64_t)1 << (n - 1 - bp.K);
+  } else {
+    bp.mode = 2;
+    bp.K = f.k;
+    for (int j = 0; j < bp.K; ++j) pos[j] = f.q[j];
+    bp.items = (uint64_t)1 << (n - bp.K);
+  }
+  for (int j = 0; j < SV_MAX_K; ++j) {
+    bp.lowmask[j] = j < bp.K ? ((uint64_t)1 << pos[j]) - 1 : 0;
+    bp.stride[j] = j < bp.K ? (uint64_t)1 << pos[j] : 0;
+  }
+  bp.mat = mat;
+}
+
+}  // namespace
+
+int batch_lds_max_n() {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  return g_lds_max_n;
+}
+void set_batch_lds_max_n(int n) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  g_lds_max_n = std::max(1, std::min(13, n));
+}
+
+int plan_fusion(const sv_gate* g, size_t n, int n_qubits, const sv_run_opts& o, std::vector<FusedGate>& fused,
+                std::vector<int32_t>& block_of);
+
+// Batched run on explicit buffers; lds_max_n < 0 uses the tuned limit.
+void batch_run_impl(void* const* psis, const int* ns, const sv_gate* const* circuits, const size_t* n_gates,
+                    size_t n_circ, const sv_run_opts& o, hipStream_t st, int lds_max_n, double* gpu_s,
+                    uint64_t* passes_out, double* fuse_s) {
+  const int lds_n = lds_max_n < 0 ? batch_lds_max_n() : lds_max_n;
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<BCirc> circs(n_circ);
+  std::vector<BPass> passes;
+  std::vector<float> mats;  // complex64, interleaved
+  int max_levels = 0;
+  for (size_t c = 0; c < n_circ; ++c) {
+    std::vector<FusedGate> fused;
+    std::vector<int32_t> block_of;
+    plan_fusion(circuits[c], n_gates[c], ns[c], o, fused, block_of);
+    circs[c].psi = (float2*)psis[c];
+    circs[c].n = ns[c];
+    circs[c].pass0 = (int)passes.size();
+    circs[c].npass = (int)fused.size();
+    for (auto& f : fused) {
+      BPass bp{};
+      fill_pass(bp, ns[c], f, (uint32_t)(mats.size() / 2));
+      passes.push_back(bp);
+      for (double v : f.mat) mats.push_back((float)v);
+    }
+    if (ns[c] > lds_n) max_levels = std::max(max_levels, (int)fused.size());
+  }
+  if (fuse_s) *fuse_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  // LDS-resident circuits and, per level, the active large circuits
+  std::vector<int> small;
+  for (size_t c = 0; c < n_circ; ++c)
+    if (ns[c] <= lds_n && circs[c].npass > 0) small.push_back((int)c);
+  int small_n = 1;
+  for (int c : small) small_n = std::max(small_n, ns[c]);
+  std::vector<std::vector<int>> active(max_levels);
+  std::vector<std::vector<uint64_t>> first(max_levels);
+  size_t level_ints = 0, level_u64 = 0;
+  for (int L = 0; L < max_levels; ++L) {
+    uint64_t acc = 0;
+    for (size_t c = 0; c < n_circ; ++c) {
+      if (ns[c] <= lds_n || circs[c].npass <= L) continue;
+      active[L].push_back((int)c);
+      first[L].push_back(acc);
+      acc += (passes[circs[c].pass0 + L].items + 255) / 256;
+    }
+    first[L].push_back(acc);
+    level_ints += active[L].size();
+    level_u64 += first[L].size();
+  }
+  // one device buffer: circuits | passes | first-block prefixes | ints | matrices
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t off_circ = 0;
+  const size_t off_pass = al(off_circ + sizeof(BCirc) * n_circ);
+  const size_t off_first = al(off_pass + sizeof(BPass) * passes.size());
+  const size_t off_int = al(off_first + sizeof(uint64_t) * level_u64);
+  const size_t off_mat = al(off_int + sizeof(int) * (level_ints + small.size()));
+  const size_t total = al(off_mat + sizeof(float) * mats.size());
+  std::vector<unsigned char> host(total, 0);
+  std::memcpy(host.data() + off_circ, circs.data(), sizeof(BCirc) * n_circ);
+  std::memcpy(host.data() + off_pass, passes.data(), sizeof(BPass) * passes.size());
+  std::vector<size_t> lvl_first_off(max_levels), lvl_int_off(max_levels);
+  size_t fu = 0, iu = 0;
+  for (int L = 0; L < max_levels; ++L) {
+    lvl_first_off[L] = off_first + sizeof(uint64_t) * fu;
+    std::memcpy(host.data() + lvl_first_off[L], first[L].data(), sizeof(uint64_t) * first[L].size());
+    fu += first[L].size();
+    lvl_int_off[L] = off_int + sizeof(int) * iu;
+    std::memcpy(host.data() + lvl_int_off[L], active[L].data(), sizeof(int) * active[L].size());
+    iu += active[L].size();
+  }
+  const size_t small_off = off_int + sizeof(int) * iu;
+  std::memcpy(host.data() + small_off, small.data(), sizeof(int) * small.size());
+  std::memcpy(host.data() + off_mat, mats.data(), sizeof(float) * mats.size());
+
+  unsigned char* dev = nullptr;
+  unsigned char* pinned = nullptr;
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr, e0 = nullptr, e1 = nullptr;
+  hipGraphExec_t exec = nullptr;
+  auto cleanup = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (side) (void)hipStreamDestroy(side);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (dev) (void)hipFree(dev);
+    if (pinned) (void)hipHostFree(pinned);
+  };
+  try {
+    SV_HIP(hipMalloc(&dev, total));
+    SV_HIP(hipHostMalloc(&pinned, total, hipHostMallocDefault));
+    std::memcpy(pinned, host.data(), total);
+    SV_HIP(hipMemcpyAsync(dev, pinned, total, hipMemcpyHostToDevice, st));
+    SV_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    SV_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    SV_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+    SV_HIP(hipEventCreate(&e0));
+    SV_HIP(hipEventCreate(&e1));
+    const BCirc* d_circ = (const BCirc*)(dev + off_circ);
+    const BPass* d_pass = (const BPass*)(dev + off_pass);
+    const float2* d_mat = (const float2*)(dev + off_mat);
+    const bool graph = st != nullptr;
+    if (graph) SV_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+      hipStream_t sst = st;
+      if (graph && !small.empty()) {  // fork: LDS branch on the side stream
+        SV_HIP(hipEventRecord(fork, st));
+        SV_HIP(hipStreamWaitEvent(side, fork, 0));
+        sst = side;
+      }
+      if (!small.empty()) {
+        hipLaunchKernelGGL(k_batch_lds, dim3((unsigned)small.size()), dim3(256), (size_t)8 << small_n, sst, d_circ,
+                           (const int*)(dev + small_off), d_pass, d_mat);
+        SV_HIP(hipGetLastError());
+      }
+      for (int L = 0; L < max_levels; ++L) {
+        const uint64_t blocks = first[L].back();
+        if (blocks == 0) continue;
+        if (blocks >= ((uint64_t)1 << 31)) throw DeviceError{hipErrorInvalidValue, "batch level too large"};
+        hipLaunchKernelGGL(k_batch_level, dim3((unsigned)blocks), dim3(256), 0, st, d_circ,
+                           (const int*)(dev + lvl_int_off[L]), (const uint64_t*)(dev + lvl_first_off[L]),
+                           (int)active[L].size(), L, d_pass, d_mat);
+        SV_HIP(hipGetLastError());
+      }
+      if (graph && !small.empty()) {  // join
+        SV_HIP(hipEventRecord(join, side));
+        SV_HIP(hipStreamWaitEvent(st, join, 0));
+      }
+    } catch (...) {
+      if (graph) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(st, &g);
+        if (g) (void)hipGraphDestroy(g);
+      }
+      throw;
+    }
+    if (graph) {
+      hipGraph_t g = nullptr;
+      SV_HIP(hipStreamEndCapture(st, &g));
+      hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) throw DeviceError{e, "hipGraphInstantiate"};
+      SV_HIP(hipEventRecord(e0, st));
+      SV_HIP(hipGraphLaunch(exec, st));
+      SV_HIP(hipEventRecord(e1, st));
+    } else {
+      SV_HIP(hipEventRecord(e0, st));
+      SV_HIP(hipEventRecord(e1, st));
+    }
+    SV_HIP(hipStreamSynchronize(st));
+    if (gpu_s) {
+      float ms = 0.f;
+      if (graph) SV_HIP(hipEventElapsedTime(&ms, e0, e1));
+      *gpu_s = ms * 1e-3;
+    }
+    if (passes_out) *passes_out = passes.size();
+    cleanup();
+  } catch (...) {
+    cleanup();
+    throw;
+  }
+}
+
+int validate_gates(const sv_gate* g, size_t n, int n_qubits);
+
+}  // namespace sv
+
+using namespace sv;
+
+extern "C" int sv_batch_run(sv_state* const* states, const sv_gate* const* circuits, const size_t* n_gates,
+                            size_t n_circuits, const sv_run_opts* opts, sv_run_stats* stats) {
+  if (n_circuits == 0) return SV_OK;
+  if (!states || !circuits || !n_gates) return fail(SV_EINVAL, "NULL argument");
+  sv_run_opts o{};
+  if (opts) {
+    o = *opts;
+  } else {
+    o.max_k = 4;
+    o.fusion = SV_FUSE_GREEDY;
+  }
+  if (o.fusion < SV_FUSE_NONE || o.fusion > SV_FUSE_LEARNED || (o.fusion != SV_FUSE_NONE && (o.max_k < 1 || o.max_k > SV_MAX_K)))
+    return fail(SV_EINVAL, "opts invalid");
+  std::vector<void*> psis(n_circuits);
+  std::vector<int> ns(n_circuits);
+  for (size_t c = 0; c < n_circuits; ++c) {
+    if (!states[c]) return fail(SV_EINVAL, "states[" + std::to_string(c) + "] is NULL");
+    if (state_poisoned(states[c])) return fail(SV_ESTATE, "a handle is poisoned");
+    ns[c] = state_n(states[c]);
+    if (ns[c] > 30) return fail(SV_EINVAL, "batched circuits are limited to 30 qubits");
+    psis[c] = state_psi(states[c]);
+    if (int rc = validate_gates(circuits[c], n_gates[c], ns[c])) return rc;
+  }
+  // batched passes run on the VALU kernels; the precision field only selects FP32
+  o.precision = SV_PREC_FP32_VALU;
+  try {
+    double gpu_s = 0, fuse_s = 0;
+    uint64_t np = 0;
+    batch_run_impl(psis.data(), ns.data(), circuits, n_gates, n_circuits, o, state_stream(states[0]), -1, &gpu_s,
+                   &np, &fuse_s);
+    if (stats) {
+      *stats = sv_run_stats{};
+      uint64_t gi = 0;
+      for (size_t c = 0; c < n_circuits; ++c) gi += n_gates[c];
+      stats->gates_in = gi;
+      stats->passes = np;
+      stats->gpu_s = gpu_s;
+      stats->fuse_s = fuse_s;
+    }
+    return SV_OK;
+  } catch (const DeviceError& e) {
+    state_poison(states[0]);
+    return fail(SV_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.err));
+  } catch (const std::bad_alloc&) {
+    return fail(SV_ENOMEM, "host allocation failed");
+  }
 }

@@ -84,11 +84,20 @@ __device__ __forceinline__ uint64_t mf_off(int l, const MfmaArgs& a) {
   return o;
 }
 
+// Register policy: with every output tile unrolled the compiler keeps all
+// accumulators and A fragments live.  That fits two waves per SIMD for the
+// BF16/FP32 PAIR layout; the Q0 layout and FP16 (two accumulator sets) keep
+// the output-tile loop rolled and ask for two waves per SIMD instead.
+template <int PREC, int LAYOUT>
+struct MfmaPolicy {
+  static constexpr bool rolled = LAYOUT == kLayoutQ0 || PREC == SV_PREC_FP16X3;
+};
+
 // PREC: SV_PREC_FP32_MFMA, SV_PREC_BF16X3 or SV_PREC_FP16X3.
 template <int K, int PREC, int LAYOUT>
-__global__ __launch_bounds__(256) void k_apply_mfma(float4* __restrict__ psi, const float4* __restrict__ Ag,
-                                                    const MfmaArgs a) {
-  extern __shared__ float4 lds4[];
+__device__ __forceinline__ void mfma_body(float4* __restrict__ psi, const float4* __restrict__ Ag, const MfmaArgs& a,
+                                          float4* lds4) {
+  constexpr int MT_UNROLL = MfmaPolicy<PREC, LAYOUT>::rolled ? 1 : (2 << K) / 32;
   constexpr int DK = 1 << K;                 // amplitudes per group
   constexpr int MT = (2 * DK) / 32;          // 32-row output tiles
   constexpr bool SPLIT = PREC != SV_PREC_FP32_MFMA;
@@ -122,7 +131,7 @@ __global__ __launch_bounds__(256) void k_apply_mfma(float4* __restrict__ psi, co
         }
       }
       const float* A = reinterpret_cast<const float*>(lds4);
-#pragma unroll
+#pragma unroll MT_UNROLL
       for (int mt = 0; mt < MT; ++mt) {
         f32x16 acc[COLS];
 #pragma unroll
@@ -192,7 +201,7 @@ __global__ __launch_bounds__(256) void k_apply_mfma(float4* __restrict__ psi, co
           }
       }
       const frag_t* A = reinterpret_cast<const frag_t*>(lds4);
-#pragma unroll
+#pragma unroll MT_UNROLL
       for (int mt = 0; mt < MT; ++mt) {
         f32x16 acc[COLS], cor[COLS];
 #pragma unroll
@@ -239,6 +248,20 @@ __global__ __launch_bounds__(256) void k_apply_mfma(float4* __restrict__ psi, co
   }
 }
 
+template <int K, int PREC, int LAYOUT>
+__global__ __launch_bounds__(256) void k_apply_mfma(float4* __restrict__ psi, const float4* __restrict__ Ag,
+                                                    const MfmaArgs a) {
+  extern __shared__ float4 lds4[];
+  mfma_body<K, PREC, LAYOUT>(psi, Ag, a, lds4);
+}
+
+template <int K, int PREC, int LAYOUT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_apply_mfma_rolled(
+    float4* __restrict__ psi, const float4* __restrict__ Ag, const MfmaArgs a) {
+  extern __shared__ float4 lds4[];
+  mfma_body<K, PREC, LAYOUT>(psi, Ag, a, lds4);
+}
+
 size_t frag_bytes(int k, int prec) {
   const int dk = 1 << k, mt = 2 * dk / 32;
   if (prec == SV_PREC_FP32_MFMA) return (size_t)mt * dk * 64 * 4;
@@ -258,8 +281,12 @@ void launch_t(const MfmaArgs& a, void* psi, const unsigned char* data, hipStream
   const size_t lds = frag_bytes(K, PREC);
   uint64_t blocks = (a.tiles + 3) / 4;
   if (blocks > 2048) blocks = 2048;
-  hipLaunchKernelGGL((k_apply_mfma<K, PREC, LAYOUT>), dim3((unsigned)blocks), dim3(256), lds, st, (float4*)psi,
-                     (const float4*)data, a);
+  if constexpr (MfmaPolicy<PREC, LAYOUT>::rolled)
+    hipLaunchKernelGGL((k_apply_mfma_rolled<K, PREC, LAYOUT>), dim3((unsigned)blocks), dim3(256), lds, st,
+                       (float4*)psi, (const float4*)data, a);
+  else
+    hipLaunchKernelGGL((k_apply_mfma<K, PREC, LAYOUT>), dim3((unsigned)blocks), dim3(256), lds, st, (float4*)psi,
+                       (const float4*)data, a);
 }
 
 template <int PREC, int LAYOUT>

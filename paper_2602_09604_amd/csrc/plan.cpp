@@ -66,13 +66,23 @@ static bool lds_feasible(int n, int k, const int* s, int tile_bits) {
   return n >= 8 && k <= SV_MAX_K;
 }
 
+int tuned_variant(int n, int k, const int* s, int precision);
+
 int choose_variant(int n, int k, const int* s, int precision, int requested) {
   const Shape sh = tuned_shape(V_LDS, n, k, s, precision);
-  if (requested == V_MFMA) return mfma_supported(k, precision) && n >= k + 6 ? V_MFMA : V_REG;
+  const bool mfma_ok = mfma_supported(k, precision) && n >= k + 6;
+  if (requested == V_MFMA) return mfma_ok ? V_MFMA : V_REG;
   if (requested == V_LDS) return lds_feasible(n, k, s, sh.tile_bits) ? V_LDS : V_REG;
   if (requested == V_REG) return V_REG;
-  if (precision != SV_PREC_FP32_VALU && k >= 4 && mfma_supported(k, precision) && n >= k + 6) return V_MFMA;
-  if (has_low_target(k, s) && lds_feasible(n, k, s, sh.tile_bits)) return V_LDS;
+  // AUTO: the autotuner's measurement for this pass class when there is one
+  const int tv = tuned_variant(n, k, s, precision);
+  if (tv == V_MFMA && mfma_ok) return V_MFMA;
+  if (tv == V_LDS && lds_feasible(n, k, s, sh.tile_bits)) return V_LDS;
+  if (tv == V_REG) return V_REG;
+  // untuned defaults, from sweeps at 30 qubits: matrix cores for k >= 4 when
+  // the precision asks for them; LDS staging for low targets up to k = 4
+  if (precision != SV_PREC_FP32_VALU && mfma_ok) return V_MFMA;
+  if (has_low_target(k, s) && k <= 4 && lds_feasible(n, k, s, sh.tile_bits)) return V_LDS;
   return V_REG;
 }
 

@@ -240,6 +240,120 @@ def sv_write_amplitudes(h: int, start: int, values) -> None:
     _check(lib().sv_write_amplitudes(_vp(h), start, v.size, v.view(np.float32).ctypes.data_as(_fp)))
 
 
+def sv_batch_run(handles: Sequence[int], circuits, opts: Optional[sv_run_opts] = None) -> dict:
+    """Run circuits[c] on handles[c] with the batched kernels; returns stats."""
+    n = len(handles)
+    arrays = [GateArray(c) for c in circuits]
+    hs = (_vp * max(1, n))(*handles)
+    cps = (ctypes.POINTER(sv_gate) * max(1, n))(*[a.ptr for a in arrays])
+    counts = (ctypes.c_size_t * max(1, n))(*[a.n for a in arrays])
+    st = sv_run_stats()
+    _check(lib().sv_batch_run(hs, cps, counts, n, ctypes.byref(opts) if opts is not None else None,
+                              ctypes.byref(st)))
+    return st.as_dict()
+
+
+class Mlp:
+    """The cost-model network on the GPU (parameters and Adam state live in
+    the library; inputs are torch float32 CUDA tensors)."""
+
+    def __init__(self, width: int = 64, seed: int = 0, stream=None):
+        import torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = _vp()
+        _check(lib().sv_mlp_create(width, seed, _vp(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h.value
+        n = ctypes.c_size_t()
+        _check(lib().sv_mlp_num_params(_vp(self.h), ctypes.byref(n)))
+        self.nparams = n.value
+
+    def free(self):
+        if self.h:
+            lib().sv_mlp_free(_vp(self.h))
+            self.h = 0
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.nparams, dtype=np.float32)
+        _check(lib().sv_mlp_get_params(_vp(self.h), out.ctypes.data_as(_fp)))
+        return out
+
+    def set_params(self, p) -> None:
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.nparams
+        _check(lib().sv_mlp_set_params(_vp(self.h), p.ctypes.data_as(_fp)))
+
+    @staticmethod
+    def _dev(t, cols=None):
+        import torch
+        assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+        if cols is not None:
+            assert t.dim() == 2 and t.shape[1] == cols
+        return t
+
+    def forward(self, x) -> np.ndarray:
+        import torch
+        x = self._dev(x, SV_COST_FEATURES)
+        y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        _check(lib().sv_mlp_forward(_vp(self.h), _vp(x.data_ptr()), x.shape[0], _vp(y.data_ptr())))
+        return y.cpu().numpy()
+
+    def loss_grad(self, x, t):
+        x = self._dev(x, SV_COST_FEATURES)
+        t = self._dev(t)
+        loss = ctypes.c_float()
+        g = np.empty(self.nparams, dtype=np.float32)
+        _check(lib().sv_mlp_loss_grad(_vp(self.h), _vp(x.data_ptr()), _vp(t.data_ptr()), x.shape[0],
+                                      ctypes.byref(loss), g.ctypes.data_as(_fp)))
+        return float(loss.value), g
+
+    def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+        _check(lib().sv_mlp_adam_step(_vp(self.h), lr, beta1, beta2, eps))
+
+    def train(self, x, t, epochs: int, lr: float) -> float:
+        x = self._dev(x, SV_COST_FEATURES)
+        t = self._dev(t)
+        loss = ctypes.c_float()
+        _check(lib().sv_mlp_train(_vp(self.h), _vp(x.data_ptr()), _vp(t.data_ptr()), x.shape[0], epochs, lr,
+                                  ctypes.byref(loss)))
+        return float(loss.value)
+
+    def install(self) -> None:
+        _check(lib().sv_cost_model_install(_vp(self.h)))
+
+
+def sv_cost_model_save(path: str) -> None:
+    _check(lib().sv_cost_model_save(os.fsencode(path)))
+
+
+def sv_cost_model_load(path: str) -> None:
+    _check(lib().sv_cost_model_load(os.fsencode(path)))
+
+
+def sv_cost_model_predict(k: int, qubits, n: int, precision: int) -> float:
+    q = np.ascontiguousarray(qubits, dtype=np.int32)
+    out = ctypes.c_double()
+    _check(lib().sv_cost_model_predict(k, q.ctypes.data_as(_i32p), n, precision, ctypes.byref(out)))
+    return out.value
+
+
+def sv_autotune(h: int, budget_ms: int = 0) -> None:
+    _check(lib().sv_autotune(_vp(h), int(budget_ms)))
+
+
+def sv_tune_save(path: str) -> None:
+    _check(lib().sv_tune_save(os.fsencode(path)))
+
+
+def sv_tune_load(path: str) -> None:
+    _check(lib().sv_tune_load(os.fsencode(path)))
+
+
 def sv_cost_features(k: int, qubits, n: int, precision: int) -> np.ndarray:
     q = np.ascontiguousarray(qubits, dtype=np.int32)
     out = np.zeros(SV_COST_FEATURES, dtype=np.float32)

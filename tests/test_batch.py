@@ -1,0 +1,88 @@
+"""Batched kernels (LDS-resident small circuits + level-synchronous large
+ones, one captured graph) against the oracle, circuit by circuit."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import circuits as C
+import oracle
+from paper_2602_09604_amd import sv
+
+pytestmark = pytest.mark.gpu
+
+
+def set_lds_limit(tmp_path, n):
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps({"format": "libsv-tune-1", "batch_lds_max_n": n, "entries": []}))
+    sv.sv_tune_load(str(p))
+
+
+def run_batch(ns, circs, max_k=4, fusion="greedy"):
+    import torch
+    stream = torch.cuda.current_stream()
+    states = [sv.State(n, stream=stream) for n in ns]
+    try:
+        stats = sv.sv_batch_run([s.h for s in states], circs, sv.make_opts(max_k=max_k, fusion=fusion))
+        out = [s.read() for s in states]
+    finally:
+        for s in states:
+            s.free()
+    return out, stats
+
+
+@pytest.mark.parametrize("lds_limit", [13, 11, 1])
+def test_batched_ansatz_small(tmp_path, lds_limit):
+    """24 circuits, n in [10, 16]: with limit 13 the small ones stay in LDS and
+    the rest go level by level; with limit 1 everything goes level by level."""
+    set_lds_limit(tmp_path, lds_limit)
+    ns, circs = C.batched_ansatz(24, seed=3, n_min=10, n_max=16)
+    out, stats = run_batch(ns, circs)
+    print("limit", lds_limit, "passes", stats["passes"], "gpu_s", stats["gpu_s"], flush=True)
+    assert stats["gates_in"] == sum(len(c) for c in circs)
+    for n, c, got in zip(ns, circs, out):
+        r = oracle.compare(got, oracle.apply_circuit(n, c))
+        assert r["max_abs"] <= 1e-5 and r["infidelity"] <= 1e-6, (n, r)
+
+
+def test_batched_ansatz_full_range(tmp_path):
+    """A slice of the 512-circuit workload (n up to 22), fused to k = 4 and 6."""
+    set_lds_limit(tmp_path, 12)
+    ns, circs = C.batched_ansatz(512, seed=0)
+    pick = [i for i in range(512) if ns[i] in (10, 13, 17, 22)][:8]
+    sub_ns = [ns[i] for i in pick]
+    sub = [circs[i] for i in pick]
+    refs = [oracle.apply_circuit(n, c) for n, c in zip(sub_ns, sub)]
+    for K in (4, 6):
+        out, stats = run_batch(sub_ns, sub, max_k=K)
+        for n, got, ref in zip(sub_ns, out, refs):
+            r = oracle.compare(got, ref)
+            assert r["max_abs"] <= 1e-5 and r["infidelity"] <= 1e-6, (K, n, r)
+
+
+def test_batch_matches_sequential_runs(tmp_path):
+    """Same answer as sv_apply_circuit per circuit (the unbatched path)."""
+    set_lds_limit(tmp_path, 12)
+    ns, circs = C.batched_ansatz(6, seed=9, n_min=11, n_max=15)
+    out, _ = run_batch(ns, circs)
+    for n, c, got in zip(ns, circs, out):
+        st = sv.State(n)
+        try:
+            st.apply_circuit(c, max_k=4)
+            ref = st.read()
+        finally:
+            st.free()
+        assert np.max(np.abs(got - ref)) < 1e-5
+
+
+def test_batch_validation():
+    st = sv.State(10)
+    try:
+        with pytest.raises(sv.SvError) as e:
+            sv.sv_batch_run([st.h], [[C.Gate((10,), C.H)]])
+        assert e.value.code == sv.SV_EINVAL
+        assert sv.sv_batch_run([], [])["passes"] == 0
+    finally:
+        st.free()

@@ -1,0 +1,100 @@
+"""Learned fusion: model file handling (CPU), corpus + GPU training + learned
+partition parity and wall time against greedy max-k (GPU)."""
+import os
+import struct
+
+import numpy as np
+import pytest
+
+import circuits as C
+import oracle
+from paper_2602_09604_amd import sv
+
+needs_lib = pytest.mark.skipif(not os.path.exists(sv.LIB_PATH), reason="libsv.so not built")
+
+
+@needs_lib
+@pytest.mark.parametrize("blob", [
+    b"",
+    b"XXXX" + struct.pack("<4I", 1, 64, 40, 6849),
+    struct.pack("<5I", 0x4D435653, 2, 64, 40, 6849),           # bad version
+    struct.pack("<5I", 0x4D435653, 1, 32, 40, 6849),           # bad width
+    struct.pack("<5I", 0x4D435653, 1, 64, 40, 6849) + b"\0" * 100,  # truncated
+    struct.pack("<5I", 0x4D435653, 1, 64, 40, 6849) + struct.pack("<f", float("nan")) * 6849,
+])
+def test_cost_model_file_rejects_malformed(tmp_path, blob):
+    p = tmp_path / "m.bin"
+    p.write_bytes(blob)
+    with pytest.raises(sv.SvError) as e:
+        sv.sv_cost_model_load(str(p))
+    assert e.value.code == sv.SV_EINVAL
+
+
+@needs_lib
+def test_cost_model_file_roundtrip_and_predict(tmp_path):
+    """A hand-made parameter file: all weights zero except b3 = 1.5, so every
+    prediction is 1.5; reload and predict through the ABI."""
+    p = np.zeros(6849, dtype=np.float32)
+    p[-1] = 1.5
+    path = tmp_path / "m.bin"
+    path.write_bytes(struct.pack("<5I", 0x4D435653, 1, 64, 40, 6849) + p.tobytes())
+    sv.sv_cost_model_load(str(path))
+    assert sv.sv_cost_model_predict(3, [0, 5, 9], 30, 0) == pytest.approx(1.5)
+    out = tmp_path / "m2.bin"
+    sv.sv_cost_model_save(str(out))
+    assert out.read_bytes() == path.read_bytes()
+
+
+@needs_lib
+def test_learned_fusion_with_constant_model_is_valid(tmp_path):
+    """With any installed model the learned partition is still a valid fusion:
+    equal state through the oracle, coverage, per-qubit order."""
+    p = np.zeros(6849, dtype=np.float32)
+    p[-1] = -5.0
+    path = tmp_path / "m.bin"
+    path.write_bytes(struct.pack("<5I", 0x4D435653, 1, 64, 40, 6849) + p.tobytes())
+    sv.sv_cost_model_load(str(path))
+    n = 10
+    gates = C.grid_circuit(2, 5, 10, seed=3)
+    fused, block_of = sv.sv_fuse(gates, n, sv.make_opts(max_k=5, fusion="learned"))
+    assert all(f.k <= 5 for f in fused)
+    assert sorted(set(block_of.tolist())) == list(range(len(fused)))
+    ref = oracle.apply_circuit(n, gates)
+    assert np.max(np.abs(oracle.apply_circuit(n, fused) - ref)) < 1e-12
+
+
+@pytest.mark.gpu
+def test_corpus_training_and_learned_partition():
+    import torch
+    from paper_2602_09604_amd import costmodel
+    st = sv.State(20)
+    try:
+        sv.sv_autotune(st.h, 0)
+    finally:
+        st.free()
+    corpus = costmodel.collect_corpus(samples=600, ns=(18, 20, 22), seed=5, log=print)
+    info = costmodel.train_cost_model(corpus, epochs=1500, lr=3e-3, seed=2)
+    print(info, flush=True)
+    assert info["test_spearman"] > 0.6, info
+    # learned partition on a held-out circuit: parity and wall time
+    n = 22
+    gates = C.grid_circuit(2, 11, 16, seed=77)
+    ref = oracle.apply_circuit(n, gates)
+    times = {}
+    for name, kw in {"learned": dict(fusion="learned", max_k=6),
+                     "greedy4": dict(fusion="greedy", max_k=4),
+                     "greedy6": dict(fusion="greedy", max_k=6)}.items():
+        st = sv.State(n)
+        try:
+            best = 1e9
+            for _ in range(3):
+                st.set_basis(0)
+                s = st.apply_circuit(gates, precision="bf16x3", stats=True, **kw)
+                best = min(best, s["gpu_s"])
+            r = oracle.compare(st.read(), ref)
+            assert r["max_abs"] <= 1e-5 and r["infidelity"] <= 1e-6, (name, r)
+            times[name] = best
+        finally:
+            st.free()
+    print(times, flush=True)
+    assert times["learned"] <= 1.25 * min(times["greedy4"], times["greedy6"]), times

@@ -1,14 +1,20 @@
 """Benchmark: a 34-qubit random grid circuit (2x17 lattice, depth 24, 1110
 gates) simulated on one MI355X through libsv.
 
+Before the timed region: the autotuner times the kernel variants on a
+scratch state; the simulator times its own passes (the cost-model corpus) and
+trains the fusion cost model on the GPU.
+
 One step = |0..0> initialisation, fusion + every gate pass of the circuit
 (sv_apply_circuit), the FP64 norm reduction and a 2^20-amplitude read-back.
 The timed region holds exactly --steps steps between device synchronisations.
 
-Printed (one JSON line on stdout): gates/s of the configured path, the plain
-unfused FP32 path measured on the same GPU for comparison, the roofline of the
-dominant pass kernel (HIP events around every pass), and the CPU oracle timed
-on a bounded sample.  Progress goes to stderr.
+Printed (one JSON line on stdout): gates/s of the configured path (default:
+learned fusion, split-FP16 matrix cores), the roofline of the dominant pass
+kernel (HIP events around every pass), the CPU oracle timed on a bounded
+sample, and in `extra` the greedy max-k and plain unfused FP32 runs of the same
+circuit on the same GPU plus the batched 512-circuit workload.  Progress goes
+to stderr.
 """
 from __future__ import annotations
 
@@ -58,12 +64,10 @@ def cpu_baseline(seconds_hint: float = 20.0) -> dict:
     n = 24
     gates = C.grid_circuit(2, 12, 24, seed=0)
     oracle.build()
-    # time a prefix first and pick a sample that takes roughly seconds_hint
     probe = gates[:40]
     t0 = time.perf_counter()
     oracle.apply_circuit(n, probe)
-    dt = time.perf_counter() - t0
-    per_gate = dt / len(probe)
+    per_gate = (time.perf_counter() - t0) / len(probe)
     count = max(40, min(len(gates), int(seconds_hint / max(per_gate, 1e-9))))
     t0 = time.perf_counter()
     oracle.apply_circuit(n, gates[:count])
@@ -79,6 +83,42 @@ def cpu_baseline(seconds_hint: float = 20.0) -> dict:
     }
 
 
+def batch_figures(max_k: int) -> dict:
+    """The 512-circuit batched workload: one captured graph (sv_batch_run)
+    against one sv_apply_circuit launch sequence per circuit."""
+    import torch
+    import circuits as C
+    from paper_2602_09604_amd import sv
+    ns, circs = C.batched_ansatz(512, seed=0)
+    stream = torch.cuda.current_stream()
+    states = [sv.State(n, stream=stream) for n in ns]
+    try:
+        opts = sv.make_opts(max_k=max_k)
+        sv.sv_batch_run([s.h for s in states], circs, opts)  # warm-up (graph build, code load)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = sv.sv_batch_run([s.h for s in states], circs, opts)
+        wall_batch = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s, c in zip(states, circs):
+            s.apply_circuit(c, max_k=max_k)
+        torch.cuda.synchronize()
+        wall_seq = time.perf_counter() - t0
+        amps = sum(1 << n for n in ns)
+        return {
+            "circuits": 512, "gates": int(st["gates_in"]), "passes": int(st["passes"]),
+            "batched_gpu_s": st["gpu_s"], "batched_wall_s": wall_batch, "batched_fuse_s": st["fuse_s"],
+            "batched_circuits_per_s_gpu": 512 / st["gpu_s"],
+            "batched_circuits_per_s_wall": 512 / wall_batch,
+            "sequential_wall_s": wall_seq, "sequential_circuits_per_s": 512 / wall_seq,
+            "speedup_wall": wall_seq / wall_batch, "total_amplitudes": amps,
+        }
+    finally:
+        for s in states:
+            s.free()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,11 +126,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="grid34")
     ap.add_argument("--max-k", type=int, default=6)
-    ap.add_argument("--fusion", default="greedy")
-    ap.add_argument("--precision", default="bf16x3")
+    ap.add_argument("--fusion", default="learned", choices=["none", "greedy", "learned"])
+    ap.add_argument("--precision", default="fp16x3", choices=["fp32_valu", "fp32_mfma", "bf16x3", "fp16x3"])
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (untuned defaults)")
-    ap.add_argument("--tune-qubits", type=int, default=30)
+    ap.add_argument("--tune-qubits", type=int, default=28)
+    ap.add_argument("--corpus-samples", type=int, default=2400)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain unfused FP32 comparison run")
+    ap.add_argument("--no-greedy", action="store_true", help="skip the greedy max-k comparison run")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 512-circuit figures")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
@@ -104,7 +147,7 @@ def main():
 
     n, gates, desc = workload(args.workload)
     log("workload:", desc, "gates:", len(gates))
-    tuned = False
+    extra = {}
     if not args.no_tune:
         t0 = time.perf_counter()
         scratch = sv.State(min(args.tune_qubits, n))
@@ -112,12 +155,21 @@ def main():
         scratch.free()
         del scratch
         torch.cuda.empty_cache()
-        tuned = True
-        log("autotune: %.1f s" % (time.perf_counter() - t0))
+        extra["autotune_s"] = time.perf_counter() - t0
+        log("autotune: %.1f s" % extra["autotune_s"])
+    if args.fusion == "learned":
+        from paper_2602_09604_amd import costmodel
+        t0 = time.perf_counter()
+        corpus = costmodel.collect_corpus(samples=args.corpus_samples, seed=0, log=log)
+        info = costmodel.train_cost_model(corpus, epochs=4000, lr=3e-3, seed=0)
+        info["corpus_s"] = time.perf_counter() - t0 - info["train_s"]
+        extra["cost_model"] = info
+        torch.cuda.empty_cache()
+        log("cost model:", info)
+
     sample = 1 << 20
     st = sv.State(n)
     opts = dict(max_k=args.max_k, fusion=args.fusion, precision=args.precision, timing=True)
-
     for i in range(args.warmup):
         s, nrm = run_step(st, gates, opts, sample)
         log("warmup %d: passes %d gpu %.3f s norm %.9f" % (i, s["passes"], s["gpu_s"], nrm))
@@ -147,30 +199,44 @@ def main():
     avg_launch = agg["variant_s"][dom] / max(1, passes[dom])
     bytes_per_launch = 16.0 * (1 << n)
     achieved = bytes_per_launch / avg_launch / 1e9
-    hbm_gbps_alg = agg["variant_passes"][1:4] and (sum(passes[1:4]) * bytes_per_launch / sum(agg["variant_s"][1:4]) / 1e9)
-
-    extra = {
+    pass_time = sum(agg["variant_s"][1:4])
+    extra.update({
         "passes_per_step": int(sum(passes) / args.steps),
-        "fused_max_k": args.max_k, "fusion": args.fusion, "precision": args.precision, "autotuned": tuned,
-        "alg_hbm_GBps_passes": hbm_gbps_alg,
+        "alg_hbm_GBps_all_passes": sum(passes[1:4]) * bytes_per_launch / pass_time / 1e9,
         "gpu_s_per_step": agg["gpu_s"] / args.steps,
         "fuse_s_per_step": agg["fuse_s"] / args.steps,
+        "useful_tflops_per_s": agg["useful_flops"] / pass_time / 1e12,
         "norm_drift": max(abs(x - 1.0) for x in norms),
         "per_variant": {VARIANT_NAMES[v]: {"passes": int(passes[v]), "avg_ms": 1e3 * agg["variant_s"][v] / passes[v]}
                         for v in range(1, 4) if passes[v]},
-    }
+        "dominant_avg_launch_ms": 1e3 * avg_launch,
+    })
 
+    if not args.no_greedy and args.fusion != "greedy":
+        st.set_basis(0)
+        g = st.apply_circuit(gates, fusion="greedy", max_k=args.max_k, precision=args.precision, stats=True)
+        extra["greedy_max_k"] = {"max_k": args.max_k, "gpu_s": g["gpu_s"], "passes": g["passes"],
+                                 "gates_per_s_gpu": len(gates) / g["gpu_s"]}
+        extra["learned_over_greedy_gpu_time"] = agg["gpu_s"] / args.steps / g["gpu_s"]
+        log("greedy max_k=%d: %.3f s" % (args.max_k, g["gpu_s"]))
     if not args.no_plain:
         log("plain unfused FP32 run ...")
         st.set_basis(0)
         p = st.apply_circuit(gates, fusion="none", precision="fp32_valu", stats=True, timing=True)
         extra["plain_fp32_unfused"] = {
-            "gates_per_s": len(gates) / p["gpu_s"], "gpu_s": p["gpu_s"], "passes": p["passes"],
-            "alg_hbm_GBps": p["bytes"] / p["gpu_s"] / 1e9,
+            "gates_per_s_gpu": len(gates) / p["gpu_s"], "gpu_s": p["gpu_s"], "passes": p["passes"],
+            "alg_hbm_GBps": p["bytes"] / p["gpu_s"] / 1e9, "norm": st.norm(),
         }
-        extra["speedup_vs_plain_fp32"] = gates_per_s / extra["plain_fp32_unfused"]["gates_per_s"]
+        extra["speedup_vs_plain_fp32"] = gates_per_s / extra["plain_fp32_unfused"]["gates_per_s_gpu"]
         log("plain: %.3f s" % p["gpu_s"])
     st.free()
+    del st
+    torch.cuda.empty_cache()
+
+    if not args.no_batch:
+        log("batched 512-circuit workload ...")
+        extra["batch512"] = batch_figures(4)
+        log("batch:", extra["batch512"])
 
     cpu = None
     if not args.no_cpu:
@@ -188,7 +254,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision in ("fp32_valu", "fp32_mfma") else args.precision,
+        "dtype": {"fp32_valu": "f32", "fp32_mfma": "f32", "bf16x3": "bf16x3+f32acc",
+                  "fp16x3": "f16x3+f32acc"}[args.precision],
         "data": "synthetic",
         "config": {"workload": desc, "qubits": n, "gates": len(gates), "state": "complex64",
                    "fusion": args.fusion, "max_k": args.max_k, "precision": args.precision},

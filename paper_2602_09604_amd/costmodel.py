@@ -34,8 +34,8 @@ def _grid_like_blocks(n: int, rng: np.random.Generator):
     return [f.qubits for f in fused]
 
 
-def collect_corpus(samples: int = 1200, ns: Sequence[int] = (20, 24, 28, 30),
-                   precisions: Sequence[str] = PRECISIONS, seed: int = 0, repeats: int = 2,
+def collect_corpus(samples: int = 2400, ns: Sequence[int] = (26, 28, 30),
+                   precisions: Sequence[str] = PRECISIONS, seed: int = 0, repeats: int = 3,
                    log=None) -> Dict[str, np.ndarray]:
     """Time `samples` single passes; returns X [samples, 40], y [samples] and the raw fields."""
     import circuits as C
@@ -50,7 +50,7 @@ def collect_corpus(samples: int = 1200, ns: Sequence[int] = (20, 24, 28, 30),
             for i in range(count):
                 if not pool:
                     pool = _grid_like_blocks(n, rng)
-                if i % 2 == 0:
+                if i % 3 == 0:
                     k = int(rng.integers(1, 7))
                     qs = tuple(int(q) for q in rng.permutation(n)[:k])
                 else:
@@ -87,25 +87,44 @@ def spearman(a, b) -> float:
     return float(np.corrcoef(ra, rb)[0, 1])
 
 
-def train_cost_model(corpus: Dict[str, np.ndarray], epochs: int = 3000, lr: float = 3e-3, seed: int = 0,
-                     holdout: float = 0.2, install: bool = True, save_path: str | None = None) -> dict:
-    """Train on the GPU, report held-out error, install as the fusion cost model."""
+def train_cost_model(corpus: Dict[str, np.ndarray], epochs: int = 4000, lr: float = 3e-3, seed: int = 0,
+                     holdout: float = 0.2, install: bool = True, save_path: str | None = None,
+                     check_every: int = 200) -> dict:
+    """Train on the GPU with early stopping on a validation split (the
+    parameters with the lowest validation error are kept), report the error on
+    a separate test split and install the network as the fusion cost model."""
     import torch
     X, y = corpus["X"], corpus["y"]
     rng = np.random.Generator(np.random.PCG64(seed + 1))
     idx = rng.permutation(len(y))
     n_test = int(len(y) * holdout)
-    te, tr = idx[:n_test], idx[n_test:]
+    n_val = n_test  # early-stopping split, disjoint from the reported test split
+    te, va, tr = idx[:n_test], idx[n_test:n_test + n_val], idx[n_test + n_val:]
     m = sv.Mlp(seed=seed)
     try:
         xd = torch.tensor(X[tr], device="cuda")
         yd = torch.tensor(y[tr], device="cuda")
+        xt = torch.tensor(X[te], device="cuda") if n_test else None
+        xv = torch.tensor(X[va], device="cuda") if n_val else None
         t0 = time.perf_counter()
-        loss = m.train(xd, yd, epochs=epochs, lr=lr)
+        best = (math.inf, None, 0)
+        done = 0
+        loss = math.nan
+        while done < epochs:
+            step = min(check_every, epochs - done)
+            loss = m.train(xd, yd, epochs=step, lr=lr)
+            done += step
+            if n_val:
+                err = float(np.mean((m.forward(xv) - y[va]) ** 2))
+                if err < best[0]:
+                    best = (err, m.get_params(), done)
+        if n_val and best[1] is not None:
+            m.set_params(best[1])
         train_s = time.perf_counter() - t0
-        out = {"train_mse": loss, "train_s": train_s, "epochs": epochs, "samples": int(len(tr))}
+        out = {"train_mse": loss, "train_s": train_s, "epochs": epochs, "best_epoch": best[2],
+               "samples": int(len(tr))}
         if n_test:
-            pred = m.forward(torch.tensor(X[te], device="cuda"))
+            pred = m.forward(xt)
             out["test_rmse"] = float(np.sqrt(np.mean((pred - y[te]) ** 2)))
             out["test_spearman"] = spearman(pred, y[te])
         if install:

@@ -250,12 +250,13 @@ void batch_run_impl(void* const* psis, const int* ns, const sv_gate* const* circ
 
   unsigned char* dev = nullptr;
   unsigned char* pinned = nullptr;
-  hipStream_t side = nullptr;
+  hipStream_t side = nullptr, own = nullptr;
   hipEvent_t fork = nullptr, join = nullptr, e0 = nullptr, e1 = nullptr;
   hipGraphExec_t exec = nullptr;
   auto cleanup = [&]() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (side) (void)hipStreamDestroy(side);
+    if (own) (void)hipStreamDestroy(own);
     if (fork) (void)hipEventDestroy(fork);
     if (join) (void)hipEventDestroy(join);
     if (e0) (void)hipEventDestroy(e0);
@@ -264,6 +265,13 @@ void batch_run_impl(void* const* psis, const int* ns, const sv_gate* const* circ
     if (pinned) (void)hipHostFree(pinned);
   };
   try {
+    if (st == nullptr) {
+      // graphs cannot be captured on the legacy default stream: drain it and
+      // run this (synchronous) call on a private blocking stream instead
+      SV_HIP(hipStreamSynchronize(nullptr));
+      SV_HIP(hipStreamCreate(&own));
+      st = own;
+    }
     SV_HIP(hipMalloc(&dev, total));
     SV_HIP(hipHostMalloc(&pinned, total, hipHostMallocDefault));
     std::memcpy(pinned, host.data(), total);
@@ -276,7 +284,7 @@ void batch_run_impl(void* const* psis, const int* ns, const sv_gate* const* circ
     const BCirc* d_circ = (const BCirc*)(dev + off_circ);
     const BPass* d_pass = (const BPass*)(dev + off_pass);
     const float2* d_mat = (const float2*)(dev + off_mat);
-    const bool graph = st != nullptr;
+    const bool graph = true;
     if (graph) SV_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     try {
       hipStream_t sst = st;
@@ -319,9 +327,6 @@ void batch_run_impl(void* const* psis, const int* ns, const sv_gate* const* circ
       if (e != hipSuccess) throw DeviceError{e, "hipGraphInstantiate"};
       SV_HIP(hipEventRecord(e0, st));
       SV_HIP(hipGraphLaunch(exec, st));
-      SV_HIP(hipEventRecord(e1, st));
-    } else {
-      SV_HIP(hipEventRecord(e0, st));
       SV_HIP(hipEventRecord(e1, st));
     }
     SV_HIP(hipStreamSynchronize(st));

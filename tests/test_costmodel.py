@@ -72,7 +72,7 @@ def test_corpus_training_and_learned_partition():
         sv.sv_autotune(st.h, 0)
     finally:
         st.free()
-    corpus = costmodel.collect_corpus(samples=600, ns=(18, 20, 22), seed=5, log=print)
+    corpus = costmodel.collect_corpus(samples=900, ns=(22, 24), seed=5, log=print)
     info = costmodel.train_cost_model(corpus, epochs=1500, lr=3e-3, seed=2)
     print(info, flush=True)
     assert info["test_spearman"] > 0.6, info

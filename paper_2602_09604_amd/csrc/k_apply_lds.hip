@@ -12,6 +12,7 @@ struct LdsArgs {
   int hi_pos[SV_MAX_K];      // ascending state bits of the h high targets
   int pmask[SV_MAX_K];       // insertion masks of the K compute-space targets, ascending
   int pstride[SV_MAX_K];     // compute-space stride of local bit j
+  int nt;                    // stream the state non-temporally
 };
 
 // Tile slots are float4 (two amplitudes).  XOR-swizzling slot bits 0..3
@@ -34,7 +35,7 @@ __device__ __forceinline__ uint64_t tile_global(const LdsArgs& a, uint64_t tb, i
 // T: log2 amplitudes per tile.  MODE as in k_apply_reg, over the tile:
 // 0 = two groups per lane (bit 0 not a target), 1 = bit 0 is target 0,
 // 2 = one group per lane with float2 accesses (k = 6, bit 0 not a target).
-template <int T, int K, int MODE>
+template <int T, int K, int MODE, bool NT>
 __global__ __launch_bounds__(256) void k_apply_lds(float4* __restrict__ psi4,
                                                    const float2* __restrict__ U,
                                                    const LdsArgs a) {
@@ -54,7 +55,7 @@ __global__ __launch_bounds__(256) void k_apply_lds(float4* __restrict__ psi4,
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int x2 = tid + 256 * i;
-      if (SLOTS % 256 == 0 || x2 < SLOTS) r[i] = psi4[tile_global(a, tb, x2)];
+      if (SLOTS % 256 == 0 || x2 < SLOTS) r[i] = gld<NT>(psi4 + tile_global(a, tb, x2));
     }
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
@@ -98,18 +99,24 @@ __global__ __launch_bounds__(256) void k_apply_lds(float4* __restrict__ psi4,
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int x2 = tid + 256 * i;
-      if (SLOTS % 256 == 0 || x2 < SLOTS) psi4[tile_global(a, tb, x2)] = r[i];
+      if (SLOTS % 256 == 0 || x2 < SLOTS) gst<NT>(psi4 + tile_global(a, tb, x2), r[i]);
     }
     __syncthreads();
   }
 }
 
-template <int T, int K, int MODE>
-void launch_lds_t(const LdsArgs& a, void* psi, const float2* U, hipStream_t st) {
+template <int T, int K, int MODE, bool NT>
+void launch_lds_nt(const LdsArgs& a, void* psi, const float2* U, hipStream_t st) {
   const uint64_t max_blocks = 256 * 8;
   const unsigned blocks = (unsigned)(a.tiles < max_blocks ? a.tiles : max_blocks);
   constexpr size_t lds = (size_t)8 << T;
-  hipLaunchKernelGGL((k_apply_lds<T, K, MODE>), dim3(blocks), dim3(256), lds, st, (float4*)psi, U, a);
+  hipLaunchKernelGGL((k_apply_lds<T, K, MODE, NT>), dim3(blocks), dim3(256), lds, st, (float4*)psi, U, a);
+}
+
+template <int T, int K, int MODE>
+void launch_lds_t(const LdsArgs& a, void* psi, const float2* U, hipStream_t st) {
+  if (a.nt) return launch_lds_nt<T, K, MODE, true>(a, psi, U, st);
+  launch_lds_nt<T, K, MODE, false>(a, psi, U, st);
 }
 
 template <int T>
@@ -156,6 +163,7 @@ void launch_lds(const Pass& p, int n, void* psi, const float2* U, hipStream_t st
   a.m = m;
   a.h = h;
   a.tiles = (uint64_t)1 << (n - T);
+  a.nt = n >= kNtMinQubits;
   // targets below m keep their bit; high target i moves to tile bit m + i
   int loc[SV_MAX_K];
   int hi = 0;

@@ -19,7 +19,7 @@ struct RegArgs {
 // MODE 1 (Q0):   bit 0 is target 0.  The float4 holds local indices 2l'
 //   and 2l'+1; K = k-1 element-space targets at s[j]-1 for j >= 1.
 // MODE 2 (ONE):  float2 elements, one group per lane, K = k targets at s[j].
-template <int K, int MODE, typename IDX>
+template <int K, int MODE, typename IDX, bool NT>
 __global__ __launch_bounds__(256) void k_apply_reg(void* __restrict__ psi_,
                                                    const float2* __restrict__ U,
                                                    const RegArgs<IDX> a) {
@@ -31,50 +31,50 @@ __global__ __launch_bounds__(256) void k_apply_reg(void* __restrict__ psi_,
     float2* __restrict__ psi = reinterpret_cast<float2*>(psi_);
     float2 v[D];
 #pragma unroll
-    for (int l = 0; l < D; ++l) v[l] = psi[base + local_offset<K, IDX>(l, a.stride)];
+    for (int l = 0; l < D; ++l) v[l] = gld<NT>(psi + base + local_offset<K, IDX>(l, a.stride));
 #pragma unroll
     for (int r = 0; r < D; ++r) {
       float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
       for (int c = 0; c < D; ++c) cmac(acc, U[r * D + c], v[c]);
-      psi[base + local_offset<K, IDX>(r, a.stride)] = acc;
+      gst<NT>(psi + base + local_offset<K, IDX>(r, a.stride), acc);
     }
   } else {
     float4* __restrict__ psi = reinterpret_cast<float4*>(psi_);
     float4 v[D];
 #pragma unroll
-    for (int l = 0; l < D; ++l) v[l] = psi[base + local_offset<K, IDX>(l, a.stride)];
+    for (int l = 0; l < D; ++l) v[l] = gld<NT>(psi + base + local_offset<K, IDX>(l, a.stride));
 #pragma unroll
-    for (int r = 0; r < D; ++r) psi[base + local_offset<K, IDX>(r, a.stride)] = pair_row<K, MODE>(v, U, r);
+    for (int r = 0; r < D; ++r) gst<NT>(psi + base + local_offset<K, IDX>(r, a.stride), pair_row<K, MODE>(v, U, r));
   }
 }
 
-template <typename IDX, int K, int MODE>
+template <typename IDX, bool NT, int K, int MODE>
 void launch_reg_t(void* psi, const float2* U, const RegArgs<IDX>& a, hipStream_t st) {
   // 2-D grid keeps blocks * 256 below 2^32 work-items per dimension
   const uint64_t blocks = ((uint64_t)a.groups + 255) / 256;
   const uint64_t gx = blocks < 65536 ? blocks : 65536;
   const uint64_t gy = (blocks + gx - 1) / gx;
-  hipLaunchKernelGGL((k_apply_reg<K, MODE, IDX>), dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, psi,
+  hipLaunchKernelGGL((k_apply_reg<K, MODE, IDX, NT>), dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, psi,
                      U, a);
 }
 
-template <typename IDX, int MODE>
+template <typename IDX, bool NT, int MODE>
 void launch_reg_k(int K, void* psi, const float2* U, const RegArgs<IDX>& a, hipStream_t st) {
   switch (K) {
-    case 0: if constexpr (MODE == 1) { launch_reg_t<IDX, 0, MODE>(psi, U, a, st); return; } break;
-    case 1: launch_reg_t<IDX, 1, MODE>(psi, U, a, st); return;
-    case 2: launch_reg_t<IDX, 2, MODE>(psi, U, a, st); return;
-    case 3: launch_reg_t<IDX, 3, MODE>(psi, U, a, st); return;
-    case 4: launch_reg_t<IDX, 4, MODE>(psi, U, a, st); return;
-    case 5: launch_reg_t<IDX, 5, MODE>(psi, U, a, st); return;
-    case 6: if constexpr (MODE == 2) { launch_reg_t<IDX, 6, MODE>(psi, U, a, st); return; } break;
+    case 0: if constexpr (MODE == 1) { launch_reg_t<IDX, NT, 0, MODE>(psi, U, a, st); return; } break;
+    case 1: launch_reg_t<IDX, NT, 1, MODE>(psi, U, a, st); return;
+    case 2: launch_reg_t<IDX, NT, 2, MODE>(psi, U, a, st); return;
+    case 3: launch_reg_t<IDX, NT, 3, MODE>(psi, U, a, st); return;
+    case 4: launch_reg_t<IDX, NT, 4, MODE>(psi, U, a, st); return;
+    case 5: launch_reg_t<IDX, NT, 5, MODE>(psi, U, a, st); return;
+    case 6: if constexpr (MODE == 2) { launch_reg_t<IDX, NT, 6, MODE>(psi, U, a, st); return; } break;
     default: break;
   }
   throw DeviceError{hipErrorInvalidValue, "k_apply_reg: unsupported K/mode"};
 }
 
-template <typename IDX>
+template <typename IDX, bool NT>
 void launch_reg(const Pass& p, int n, void* psi, const float2* U, hipStream_t st) {
   RegArgs<IDX> a{};
   int mode, K;
@@ -99,9 +99,9 @@ void launch_reg(const Pass& p, int n, void* psi, const float2* U, hipStream_t st
     a.lowmask[j] = ((IDX)1 << pos[j]) - 1;
     a.stride[j] = (IDX)1 << pos[j];
   }
-  if (mode == 0) launch_reg_k<IDX, 0>(K, psi, U, a, st);
-  else if (mode == 1) launch_reg_k<IDX, 1>(K, psi, U, a, st);
-  else launch_reg_k<IDX, 2>(K, psi, U, a, st);
+  if (mode == 0) launch_reg_k<IDX, NT, 0>(K, psi, U, a, st);
+  else if (mode == 1) launch_reg_k<IDX, NT, 1>(K, psi, U, a, st);
+  else launch_reg_k<IDX, NT, 2>(K, psi, U, a, st);
 }
 
 }  // namespace
@@ -117,10 +117,16 @@ void launch_pass(const Pass& p, int n, void* psi, const unsigned char* arena_dev
     launch_mfma(p, n, psi, data, st);
   } else if (p.variant == V_LDS) {
     launch_lds(p, n, psi, reinterpret_cast<const float2*>(data), st);
-  } else if (n <= 32) {
-    launch_reg<uint32_t>(p, n, psi, reinterpret_cast<const float2*>(data), st);
   } else {
-    launch_reg<uint64_t>(p, n, psi, reinterpret_cast<const float2*>(data), st);
+    const bool nt = gather_nt(n, p.k, p.s);
+    const float2* U = reinterpret_cast<const float2*>(data);
+    if (n <= 32) {
+      if (nt) launch_reg<uint32_t, true>(p, n, psi, U, st);
+      else launch_reg<uint32_t, false>(p, n, psi, U, st);
+    } else {
+      if (nt) launch_reg<uint64_t, true>(p, n, psi, U, st);
+      else launch_reg<uint64_t, false>(p, n, psi, U, st);
+    }
   }
   SV_HIP(hipGetLastError());
 }

@@ -26,6 +26,66 @@
 namespace sv {
 namespace kern {
 
+// Global state accesses.  A pass streams the state once; for states beyond
+// the last-level cache the non-temporal form (NT = true) keeps the stream
+// from evicting useful lines and measured faster for in-place sweeps; small
+// states that stay cache-resident across passes use ordinary accesses.
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+
+template <bool NT>
+__device__ __forceinline__ float4 gld(const float4* p) {
+  if constexpr (NT) {
+    const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+  } else {
+    return *p;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ float2 gld(const float2* p) {
+  if constexpr (NT) {
+    const nt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f2*>(p));
+    return make_float2(v.x, v.y);
+  } else {
+    return *p;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ void gst(float4* p, const float4 v) {
+  if constexpr (NT) {
+    const nt_f4 w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<nt_f4*>(p));
+  } else {
+    *p = v;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ void gst(float2* p, const float2 v) {
+  if constexpr (NT) {
+    const nt_f2 w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<nt_f2*>(p));
+  } else {
+    *p = v;
+  }
+}
+
+// States of at least 2^26 amplitudes (512 MiB) exceed the 256 MB last-level
+// cache: stream them non-temporally.
+constexpr int kNtMinQubits = 26;
+
+// Register-gather passes stream non-temporally only when every wavefront
+// access covers whole 128-byte lines, i.e. no target in bits 1..3 (bit 0
+// lives inside the 16-byte element).  Otherwise the partial lines of one
+// access are completed by the lane's other accesses through the L2, which
+// non-temporal accesses would bypass (measured 2-10x slower).
+inline bool gather_nt(int n, int k, const int* s) {
+  if (n < kNtMinQubits) return false;
+  for (int j = 0; j < k; ++j)
+    if (s[j] >= 1 && s[j] < 4) return false;
+  return true;
+}
+
 __device__ __forceinline__ void cmac(float2& acc, const float2 u, const float2 v) {
   acc.x = fmaf(u.x, v.x, acc.x);
   acc.x = fmaf(-u.y, v.y, acc.x);

@@ -24,11 +24,13 @@
 #include <cstring>
 #include <type_traits>
 
-#include "sv_internal.h"
+#include "k_common.h"
 
 namespace sv {
 
 namespace {
+using kern::gld;
+using kern::gst;
 
 typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8;
 typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
@@ -94,7 +96,7 @@ struct MfmaPolicy {
 };
 
 // PREC: SV_PREC_FP32_MFMA, SV_PREC_BF16X3 or SV_PREC_FP16X3.
-template <int K, int PREC, int LAYOUT>
+template <int K, int PREC, int LAYOUT, bool NT>
 __device__ __forceinline__ void mfma_body(float4* __restrict__ psi, const float4* __restrict__ Ag, const MfmaArgs& a,
                                           float4* lds4) {
   constexpr int MT_UNROLL = MfmaPolicy<PREC, LAYOUT>::rolled ? 1 : (2 << K) / 32;
@@ -118,14 +120,14 @@ __device__ __forceinline__ void mfma_body(float4* __restrict__ psi, const float4
       if constexpr (LAYOUT == kLayoutPair) {
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-          const float4 f = psi[base + mf_off<KQ>(s, a)];
+          const float4 f = gld<NT>(psi + base + mf_off<KQ>(s, a));
           b[0][s] = h ? f.y : f.x;
           b[1][s] = h ? f.w : f.z;
         }
       } else {
 #pragma unroll
         for (int t = 0; t < KS / 2; ++t) {
-          const float4 f = psi[base + mf_off<KQ>(t, a)];
+          const float4 f = gld<NT>(psi + base + mf_off<KQ>(t, a));
           b[0][2 * t] = h ? f.y : f.x;
           b[0][2 * t + 1] = h ? f.w : f.z;
         }
@@ -148,12 +150,10 @@ __device__ __forceinline__ void mfma_body(float4* __restrict__ psi, const float4
         for (int q = 0; q < 4; ++q) {
           const int r = 16 * mt + 4 * q + 2 * h;  // rows 2r, 2r+1, 2r+2, 2r+3
           if constexpr (LAYOUT == kLayoutPair) {
-            psi[base + mf_off<KQ>(r, a)] = make_float4(acc[0][4 * q], acc[0][4 * q + 1], acc[1][4 * q], acc[1][4 * q + 1]);
-            psi[base + mf_off<KQ>(r + 1, a)] =
-                make_float4(acc[0][4 * q + 2], acc[0][4 * q + 3], acc[1][4 * q + 2], acc[1][4 * q + 3]);
+            gst<NT>(psi + base + mf_off<KQ>(r, a), make_float4(acc[0][4 * q], acc[0][4 * q + 1], acc[1][4 * q], acc[1][4 * q + 1]));
+            gst<NT>(psi + base + mf_off<KQ>(r + 1, a), make_float4(acc[0][4 * q + 2], acc[0][4 * q + 3], acc[1][4 * q + 2], acc[1][4 * q + 3]));
           } else {
-            psi[base + mf_off<KQ>(r >> 1, a)] =
-                make_float4(acc[0][4 * q], acc[0][4 * q + 1], acc[0][4 * q + 2], acc[0][4 * q + 3]);
+            gst<NT>(psi + base + mf_off<KQ>(r >> 1, a), make_float4(acc[0][4 * q], acc[0][4 * q + 1], acc[0][4 * q + 2], acc[0][4 * q + 3]));
           }
         }
       }
@@ -168,7 +168,7 @@ __device__ __forceinline__ void mfma_body(float4* __restrict__ psi, const float4
         if constexpr (LAYOUT == kLayoutPair) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const float4 f = psi[base + mf_off<KQ>(8 * s + 4 * h + q, a)];
+            const float4 f = gld<NT>(psi + base + mf_off<KQ>(8 * s + 4 * h + q, a));
             x[0][2 * q] = f.x;
             x[0][2 * q + 1] = f.y;
             x[1][2 * q] = f.z;
@@ -177,7 +177,7 @@ __device__ __forceinline__ void mfma_body(float4* __restrict__ psi, const float4
         } else {
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
-            const float4 f = psi[base + mf_off<KQ>(4 * s + 2 * h + q, a)];
+            const float4 f = gld<NT>(psi + base + mf_off<KQ>(4 * s + 2 * h + q, a));
             x[0][4 * q] = f.x;
             x[0][4 * q + 1] = f.y;
             x[0][4 * q + 2] = f.z;
@@ -235,12 +235,10 @@ __device__ __forceinline__ void mfma_body(float4* __restrict__ psi, const float4
         for (int q = 0; q < 4; ++q) {
           const int r = 16 * mt + 4 * q + 2 * h;
           if constexpr (LAYOUT == kLayoutPair) {
-            psi[base + mf_off<KQ>(r, a)] = make_float4(acc[0][4 * q], acc[0][4 * q + 1], acc[1][4 * q], acc[1][4 * q + 1]);
-            psi[base + mf_off<KQ>(r + 1, a)] =
-                make_float4(acc[0][4 * q + 2], acc[0][4 * q + 3], acc[1][4 * q + 2], acc[1][4 * q + 3]);
+            gst<NT>(psi + base + mf_off<KQ>(r, a), make_float4(acc[0][4 * q], acc[0][4 * q + 1], acc[1][4 * q], acc[1][4 * q + 1]));
+            gst<NT>(psi + base + mf_off<KQ>(r + 1, a), make_float4(acc[0][4 * q + 2], acc[0][4 * q + 3], acc[1][4 * q + 2], acc[1][4 * q + 3]));
           } else {
-            psi[base + mf_off<KQ>(r >> 1, a)] =
-                make_float4(acc[0][4 * q], acc[0][4 * q + 1], acc[0][4 * q + 2], acc[0][4 * q + 3]);
+            gst<NT>(psi + base + mf_off<KQ>(r >> 1, a), make_float4(acc[0][4 * q], acc[0][4 * q + 1], acc[0][4 * q + 2], acc[0][4 * q + 3]));
           }
         }
       }
@@ -248,18 +246,18 @@ __device__ __forceinline__ void mfma_body(float4* __restrict__ psi, const float4
   }
 }
 
-template <int K, int PREC, int LAYOUT>
+template <int K, int PREC, int LAYOUT, bool NT>
 __global__ __launch_bounds__(256) void k_apply_mfma(float4* __restrict__ psi, const float4* __restrict__ Ag,
                                                     const MfmaArgs a) {
   extern __shared__ float4 lds4[];
-  mfma_body<K, PREC, LAYOUT>(psi, Ag, a, lds4);
+  mfma_body<K, PREC, LAYOUT, NT>(psi, Ag, a, lds4);
 }
 
-template <int K, int PREC, int LAYOUT>
+template <int K, int PREC, int LAYOUT, bool NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_apply_mfma_rolled(
     float4* __restrict__ psi, const float4* __restrict__ Ag, const MfmaArgs a) {
   extern __shared__ float4 lds4[];
-  mfma_body<K, PREC, LAYOUT>(psi, Ag, a, lds4);
+  mfma_body<K, PREC, LAYOUT, NT>(psi, Ag, a, lds4);
 }
 
 size_t frag_bytes(int k, int prec) {
@@ -276,25 +274,28 @@ inline double a4m(const double* mat, int dk, int row, int col) {
   return pc == 0 ? ui : ur;
 }
 
-template <int K, int PREC, int LAYOUT>
+template <int K, int PREC, int LAYOUT, bool NT>
 void launch_t(const MfmaArgs& a, void* psi, const unsigned char* data, hipStream_t st) {
   const size_t lds = frag_bytes(K, PREC);
   uint64_t blocks = (a.tiles + 3) / 4;
   if (blocks > 2048) blocks = 2048;
   if constexpr (MfmaPolicy<PREC, LAYOUT>::rolled)
-    hipLaunchKernelGGL((k_apply_mfma_rolled<K, PREC, LAYOUT>), dim3((unsigned)blocks), dim3(256), lds, st,
+    hipLaunchKernelGGL((k_apply_mfma_rolled<K, PREC, LAYOUT, NT>), dim3((unsigned)blocks), dim3(256), lds, st,
                        (float4*)psi, (const float4*)data, a);
   else
-    hipLaunchKernelGGL((k_apply_mfma<K, PREC, LAYOUT>), dim3((unsigned)blocks), dim3(256), lds, st, (float4*)psi,
+    hipLaunchKernelGGL((k_apply_mfma<K, PREC, LAYOUT, NT>), dim3((unsigned)blocks), dim3(256), lds, st, (float4*)psi,
                        (const float4*)data, a);
 }
 
 template <int PREC, int LAYOUT>
-void launch_k(int k, const MfmaArgs& a, void* psi, const unsigned char* data, hipStream_t st) {
-  switch (k) {
-    case 4: return launch_t<4, PREC, LAYOUT>(a, psi, data, st);
-    case 5: return launch_t<5, PREC, LAYOUT>(a, psi, data, st);
-    case 6: return launch_t<6, PREC, LAYOUT>(a, psi, data, st);
+void launch_k(int k, bool nt, const MfmaArgs& a, void* psi, const unsigned char* data, hipStream_t st) {
+  switch (k * 2 + (nt ? 1 : 0)) {
+    case 8: return launch_t<4, PREC, LAYOUT, false>(a, psi, data, st);
+    case 9: return launch_t<4, PREC, LAYOUT, true>(a, psi, data, st);
+    case 10: return launch_t<5, PREC, LAYOUT, false>(a, psi, data, st);
+    case 11: return launch_t<5, PREC, LAYOUT, true>(a, psi, data, st);
+    case 12: return launch_t<6, PREC, LAYOUT, false>(a, psi, data, st);
+    case 13: return launch_t<6, PREC, LAYOUT, true>(a, psi, data, st);
     default: throw DeviceError{hipErrorInvalidValue, "k_apply_mfma: k must be 4..6"};
   }
 }
@@ -368,18 +369,19 @@ void launch_mfma(const Pass& p, int n, void* psi, const unsigned char* data, hip
   }
   if (a.tiles == 0) throw DeviceError{hipErrorInvalidValue, "k_apply_mfma: state too small for a 32-group tile"};
   const bool pair = layout == kLayoutPair;
+  const bool nt = kern::gather_nt(n, p.k, p.s);
   switch (p.precision) {
     case SV_PREC_FP32_MFMA:
-      pair ? launch_k<SV_PREC_FP32_MFMA, kLayoutPair>(p.k, a, psi, data, st)
-           : launch_k<SV_PREC_FP32_MFMA, kLayoutQ0>(p.k, a, psi, data, st);
+      pair ? launch_k<SV_PREC_FP32_MFMA, kLayoutPair>(p.k, nt, a, psi, data, st)
+           : launch_k<SV_PREC_FP32_MFMA, kLayoutQ0>(p.k, nt, a, psi, data, st);
       break;
     case SV_PREC_BF16X3:
-      pair ? launch_k<SV_PREC_BF16X3, kLayoutPair>(p.k, a, psi, data, st)
-           : launch_k<SV_PREC_BF16X3, kLayoutQ0>(p.k, a, psi, data, st);
+      pair ? launch_k<SV_PREC_BF16X3, kLayoutPair>(p.k, nt, a, psi, data, st)
+           : launch_k<SV_PREC_BF16X3, kLayoutQ0>(p.k, nt, a, psi, data, st);
       break;
     case SV_PREC_FP16X3:
-      pair ? launch_k<SV_PREC_FP16X3, kLayoutPair>(p.k, a, psi, data, st)
-           : launch_k<SV_PREC_FP16X3, kLayoutQ0>(p.k, a, psi, data, st);
+      pair ? launch_k<SV_PREC_FP16X3, kLayoutPair>(p.k, nt, a, psi, data, st)
+           : launch_k<SV_PREC_FP16X3, kLayoutQ0>(p.k, nt, a, psi, data, st);
       break;
     default:
       throw DeviceError{hipErrorInvalidValue, "k_apply_mfma: precision"};

@@ -1,14 +1,17 @@
 // State initialisation and the FP64 norm reduction sum |c_i|^2 (Eq. 1).
-#include "sv_internal.h"
+#include "k_common.h"
 
 namespace sv {
 
 namespace {
+using kern::gld;
+using kern::gst;
 
 constexpr int kNormBlocks = 2048;  // partials of the first level
 constexpr int kThreads = 256;
 
 // Write |index>: a single coalesced sweep of 16-byte stores.
+template <bool NT>
 __global__ __launch_bounds__(256) void k_init_basis(float4* __restrict__ psi, uint64_t pairs,
                                                     uint64_t index) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -18,7 +21,7 @@ __global__ __launch_bounds__(256) void k_init_basis(float4* __restrict__ psi, ui
       if (index & 1) v.z = 1.f;
       else v.x = 1.f;
     }
-    psi[i] = v;
+    gst<NT>(psi + i, v);
   }
 }
 
@@ -46,6 +49,7 @@ __device__ double block_sum(double v) {
 
 // Level 1: each block owns a contiguous slice of float4 pairs; FP32 squares
 // promoted to FP64 before accumulation.
+template <bool NT>
 __global__ __launch_bounds__(256) void k_norm_partial(const float4* __restrict__ psi, uint64_t pairs,
                                                       double* __restrict__ partials) {
   const uint64_t per = (pairs + gridDim.x - 1) / gridDim.x;
@@ -53,7 +57,7 @@ __global__ __launch_bounds__(256) void k_norm_partial(const float4* __restrict__
   const uint64_t hi = lo + per < pairs ? lo + per : pairs;
   double acc = 0.0;
   for (uint64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
-    const float4 v = psi[i];
+    const float4 v = gld<NT>(psi + i);
     acc = fma((double)v.x, (double)v.x, acc);
     acc = fma((double)v.y, (double)v.y, acc);
     acc = fma((double)v.z, (double)v.z, acc);
@@ -91,7 +95,10 @@ void launch_init_basis(void* psi, int n, uint64_t index, hipStream_t st) {
     const uint64_t pairs = (uint64_t)1 << (n - 1);
     uint64_t blocks = (pairs + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_init_basis, dim3((unsigned)blocks), dim3(256), 0, st, (float4*)psi, pairs, index);
+    if (n >= kern::kNtMinQubits)
+      hipLaunchKernelGGL(k_init_basis<true>, dim3((unsigned)blocks), dim3(256), 0, st, (float4*)psi, pairs, index);
+    else
+      hipLaunchKernelGGL(k_init_basis<false>, dim3((unsigned)blocks), dim3(256), 0, st, (float4*)psi, pairs, index);
   }
   SV_HIP(hipGetLastError());
 }
@@ -104,8 +111,12 @@ void launch_norm(const void* psi, int n, double* partials, int max_parts, double
     uint64_t blocks = (pairs + 1023) / 1024;  // at least 4 pairs per thread
     if (blocks > (uint64_t)max_parts) blocks = max_parts;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_norm_partial, dim3((unsigned)blocks), dim3(256), 0, st, (const float4*)psi, pairs,
-                       partials);
+    if (n >= kern::kNtMinQubits)
+      hipLaunchKernelGGL(k_norm_partial<true>, dim3((unsigned)blocks), dim3(256), 0, st, (const float4*)psi, pairs,
+                         partials);
+    else
+      hipLaunchKernelGGL(k_norm_partial<false>, dim3((unsigned)blocks), dim3(256), 0, st, (const float4*)psi, pairs,
+                         partials);
     hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, st, (const double*)partials, (int)blocks, out);
   }
   SV_HIP(hipGetLastError());

@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "gates/s + HBM GB/s (34q c64); fused+MFMA vs plain FP32 at infidelity≤1e-6"
 HBM_PEAK_GBPS = 8000.0
-VARIANT_NAMES = {1: "k_apply_reg", 2: "k_apply_lds", 3: "k_apply_mfma"}
+VARIANT_NAMES = {1: "k_apply_reg", 2: "k_apply_lds", 3: "k_apply_mfma", 4: "k_phase"}
 
 
 def log(*a):
@@ -248,7 +248,7 @@ def main():
         else:
             for key in ("gpu_s", "fuse_s", "useful_flops"):
                 agg[key] += s[key]
-            for v in range(4):
+            for v in range(5):
                 agg["variant_s"][v] += s["variant_s"][v]
                 agg["variant_passes"][v] += s["variant_passes"][v]
     torch.cuda.synchronize()
@@ -256,20 +256,20 @@ def main():
     ms_per_step = wall / args.steps * 1e3
     gates_per_s = len(gates) / (wall / args.steps)
     passes = agg["variant_passes"]
-    dom = max(range(1, 4), key=lambda v: agg["variant_s"][v])
+    dom = max(range(1, 5), key=lambda v: agg["variant_s"][v])
     avg_launch = agg["variant_s"][dom] / max(1, passes[dom])
     bytes_per_launch = 16.0 * (1 << n)
     achieved = bytes_per_launch / avg_launch / 1e9
-    pass_time = sum(agg["variant_s"][1:4])
+    pass_time = sum(agg["variant_s"][1:5])
     extra.update({
         "passes_per_step": int(sum(passes) / args.steps),
-        "alg_hbm_GBps_all_passes": sum(passes[1:4]) * bytes_per_launch / pass_time / 1e9,
+        "alg_hbm_GBps_all_passes": sum(passes[1:5]) * bytes_per_launch / pass_time / 1e9,
         "gpu_s_per_step": agg["gpu_s"] / args.steps,
         "fuse_s_per_step": agg["fuse_s"] / args.steps,
         "useful_tflops_per_s": agg["useful_flops"] / pass_time / 1e12,
         "norm_drift": max(abs(x - 1.0) for x in norms),
         "per_variant": {VARIANT_NAMES[v]: {"passes": int(passes[v]), "avg_ms": 1e3 * agg["variant_s"][v] / passes[v]}
-                        for v in range(1, 4) if passes[v]},
+                        for v in range(1, 5) if passes[v]},
         "dominant_avg_launch_ms": 1e3 * avg_launch,
     })
 

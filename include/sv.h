@@ -52,7 +52,8 @@ extern "C" {
  * [Yr;Yi] = [[Ur,-Ui],[Ui,Ur]] [Xr;Xi] on FP32 matrix cores.
  * BF16X3 / FP16X3: the same GEMM with every operand split into hi + lo
  * halves of the narrow type and three products (hi*hi + hi*lo + lo*hi)
- * accumulated in FP32; FP16X3 also scales each tile by a power of two. */
+ * accumulated in FP32; FP16X3 scales amplitudes by 2^14 before the split
+ * (valid for normalised states, |c| <= 1). */
 #define SV_PREC_FP32_VALU 0
 #define SV_PREC_FP32_MFMA 1
 #define SV_PREC_BF16X3 2
@@ -63,10 +64,18 @@ extern "C" {
  * by matrix product, horizontal by tensor product, per-qubit order kept);
  * LEARNED scores candidate partitions with the cost-model network loaded by
  * sv_cost_model_load and keeps the cheapest, falling back to GREEDY when no
- * model is loaded. */
+ * model is loaded.  PHASE is GREEDY in which pure-phase diagonal gates of at
+ * most two qubits (CZ, CP, RZ, Z, S, T, ...) never block one another: those
+ * that fit join dense blocks, the others are gathered into phase blocks of
+ * any width.  sv_fuse returns a phase block as its canonical diagonal gates
+ * (one CP-form gate per interacting pair, one diagonal per qubit); in
+ * sv_apply_circuit every maximal run of such gates is one elementwise pass
+ * that multiplies amplitude i by exp(i * theta(i)), theta a quadratic
+ * polynomial in the bits of i. */
 #define SV_FUSE_NONE 0
 #define SV_FUSE_GREEDY 1
 #define SV_FUSE_LEARNED 2
+#define SV_FUSE_PHASE 3
 
 /* Kernel variant of a pass (for tests and tuning; AUTO is the default).
  * REG: each lane owns whole groups in registers, gathered straight from HBM
@@ -111,8 +120,9 @@ typedef struct {
   double useful_flops;   /* sum over passes of 2^(n-k) * 2^k (8*2^k - 2) */
   double fuse_s;         /* host time in the fusion pass */
   double gpu_s;          /* device time of the passes (HIP events) */
-  double variant_s[4];   /* with opts.timing: device time per SV_VARIANT_* (index 0 unused) */
-  uint64_t variant_passes[4]; /* with opts.timing: passes per SV_VARIANT_* */
+  double variant_s[5];   /* with opts.timing: device time per kernel family: 1 register,
+                            2 LDS, 3 matrix core, 4 phase-only (index 0 unused) */
+  uint64_t variant_passes[5]; /* with opts.timing: passes per kernel family */
 } sv_run_stats;
 
 /* ---- state -------------------------------------------------------------- */

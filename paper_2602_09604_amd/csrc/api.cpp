@@ -89,10 +89,42 @@ static double useful_flops(int n, int k) {
 // captured graph).
 static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const sv_run_opts& o,
                        sv_run_stats* stats) {
-  std::vector<Pass> passes(fused.size());
+  // With PHASE fusion every maximal run of pure-phase gates (k <= 2) becomes
+  // one phase pass (or a few, when its cross-chunk terms need more hubs than
+  // one pass holds); everything else is a matrix pass.
+  std::vector<Pass> passes;
+  std::vector<const double*> mats;               // matrix passes: the fused matrix
+  std::vector<std::vector<float>> phase_data;    // phase passes: their tables
   size_t total = 0;
-  for (size_t i = 0; i < fused.size(); ++i) {
-    Pass& p = passes[i];
+  auto add = [&](Pass& p) {
+    p.mat_off = total;
+    total += align256(p.mat_bytes);
+    passes.push_back(p);
+  };
+  for (size_t i = 0; i < fused.size();) {
+    if ((o.fusion == SV_FUSE_PHASE || o.fusion == SV_FUSE_LEARNED) &&
+        is_phase_matrix(fused[i].k, fused[i].mat.data())) {
+      PhasePoly poly(s->n);
+      size_t j = i;
+      for (; j < fused.size() && is_phase_matrix(fused[j].k, fused[j].mat.data()); ++j)
+        poly.add_gate(fused[j].k, fused[j].q, fused[j].mat.data());
+      std::vector<PhaseTables> tabs;
+      phase_tables(poly, s->n, tabs);
+      for (auto& t : tabs) {
+        Pass p;
+        p.k = 0;
+        p.variant = V_PHASE;
+        p.nhubs = t.nhubs;
+        std::copy(t.hub, t.hub + t.nhubs, p.hub);
+        p.mat_bytes = sizeof(float) * t.tab.size();
+        add(p);
+        mats.push_back(nullptr);
+        phase_data.push_back(std::move(t.tab));
+      }
+      i = j;
+      continue;
+    }
+    Pass p;
     p.k = fused[i].k;
     std::copy(fused[i].q, fused[i].q + p.k, p.s);
     p.precision = o.precision;
@@ -102,15 +134,19 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
     p.reg_iters = sh.reg_iters;
     p.mfma_cols = sh.mfma_cols;
     p.mat_bytes = pass_data_bytes(p);
-    p.mat_off = total;
-    total += align256(p.mat_bytes);
+    add(p);
+    mats.push_back(fused[i].mat.data());
+    phase_data.emplace_back();
+    ++i;
   }
   if (total == 0) return;
   drop_graph(s);
   const size_t base = arena_take(s, total);
   for (size_t i = 0; i < passes.size(); ++i) {
     passes[i].mat_off += base;
-    encode_pass_data(passes[i], fused[i].mat.data(), s->arena_host + passes[i].mat_off);
+    unsigned char* dst = s->arena_host + passes[i].mat_off;
+    if (passes[i].variant == V_PHASE) std::memcpy(dst, phase_data[i].data(), passes[i].mat_bytes);
+    else encode_pass_data(passes[i], mats[i], dst);
   }
   SV_HIP(hipMemcpyAsync(s->arena_dev + base, s->arena_host + base, total, hipMemcpyHostToDevice, s->stream));
   if (stats) SV_HIP(hipEventRecord(s->ev0, s->stream));
@@ -180,7 +216,7 @@ static sv_run_opts default_opts() {
 }
 
 static int check_opts(const sv_run_opts& o) {
-  if (o.fusion < SV_FUSE_NONE || o.fusion > SV_FUSE_LEARNED) return fail(SV_EINVAL, "opts.fusion invalid");
+  if (o.fusion < SV_FUSE_NONE || o.fusion > SV_FUSE_PHASE) return fail(SV_EINVAL, "opts.fusion invalid");
   if (o.fusion != SV_FUSE_NONE && (o.max_k < 1 || o.max_k > SV_MAX_K))
     return fail(SV_EINVAL, "opts.max_k must be 1..6");
   if (o.precision < SV_PREC_FP32_VALU || o.precision > SV_PREC_FP16X3)
@@ -195,6 +231,8 @@ int plan_fusion(const sv_gate* g, size_t n, int n_qubits, const sv_run_opts& o, 
                 std::vector<int32_t>& block_of) {
   if (o.fusion == SV_FUSE_NONE) {
     fuse_none(g, n, fused, block_of);
+  } else if (o.fusion == SV_FUSE_PHASE) {
+    fuse_phase(g, n, o.max_k, fused, block_of);
   } else if (o.fusion == SV_FUSE_LEARNED) {
     if (!fuse_learned(g, n, n_qubits, o.max_k, o.precision, fused, block_of))
       fuse_greedy(g, n, o.max_k, fused, block_of);

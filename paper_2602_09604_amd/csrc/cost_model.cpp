@@ -149,6 +149,29 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
       best = cand;
     }
   }
+  // The phase-block partition: each run of phase gates is one elementwise
+  // sweep, priced as a one-qubit pass on the top qubit (same traffic, no gather).
+  std::vector<FusedGate> ph;
+  std::vector<int32_t> ph_of;
+  fuse_phase(g, n, max_k, ph, ph_of);
+  double t_ph = 0;
+  bool in_run = false;
+  for (const FusedGate& f : ph) {
+    if (is_phase_matrix(f.k, f.mat.data())) {
+      if (!in_run) t_ph += pass_ns((uint64_t)1 << (n_qubits - 1));
+      in_run = true;
+    } else {
+      in_run = false;
+      uint64_t m = 0;
+      for (int j = 0; j < f.k; ++j) m |= (uint64_t)1 << f.q[j];
+      t_ph += pass_ns(m);
+    }
+  }
+  if (t_ph < best_t) {
+    out = std::move(ph);
+    block_of = std::move(ph_of);
+    return true;
+  }
   fuse_blocks(g, n, best, out, block_of);
   return true;
 }

@@ -1,0 +1,250 @@
+// Diagonal specialisation: pure-phase gates as phase polynomials.
+//
+// A diagonal unitary on at most two qubits a, b is exp(i theta) with
+// theta = c + alpha_a x_a + alpha_b x_b + beta x_a x_b (four diagonal entries,
+// four parameters), so any run of such gates (CZ, CP, RZ, Z, S, T, ...)
+// multiplies amplitude i by exp(i theta(i)) with theta a quadratic polynomial
+// in the bits of i.  Such gates commute with one another; fusion exploits it
+// (fuse_phase) and the device applies a whole run as one elementwise pass
+// (k_phase).
+//
+// Device tables: the index is cut into 8-bit chunks.  theta(i) =
+//   sum_c T_c[chunk_c(i)]                      (linear + same-chunk terms)
+// + sum_h x_h(i) * sum_c R_hc[chunk_c(i)]      (cross-chunk terms by hub h)
+// where the hubs are a vertex cover of the cross-chunk interaction graph.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+
+#include "sv_internal.h"
+
+namespace sv {
+
+void fuse_blocks(const sv_gate* g, size_t n, const std::vector<std::vector<int>>& blocks,
+                 std::vector<FusedGate>& out, std::vector<int32_t>& block_of);
+
+namespace {
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kUnitTol = 1e-12;
+
+uint64_t qmask_of(const sv_gate& g) {
+  uint64_t m = 0;
+  for (int j = 0; j < g.k; ++j) m |= (uint64_t)1 << g.qubits[j];
+  return m;
+}
+
+double wrap(double a) {
+  a = std::fmod(a, kTwoPi);
+  return a < 0 ? a + kTwoPi : a;
+}
+}  // namespace
+
+bool is_phase_matrix(int k, const double* mat) {
+  if (k < 1 || k > 2 || !mat) return false;
+  const int d = 1 << k;
+  for (int r = 0; r < d; ++r)
+    for (int c = 0; c < d; ++c) {
+      const double re = mat[2 * (r * d + c)], im = mat[2 * (r * d + c) + 1];
+      if (r == c) {
+        if (std::fabs(std::hypot(re, im) - 1.0) > kUnitTol) return false;
+      } else if (re != 0.0 || im != 0.0) {
+        return false;
+      }
+    }
+  return true;
+}
+
+void PhasePoly::add_gate(int k, const int* q, const double* mat) {
+  auto arg = [&](int l) { return std::atan2(mat[2 * (l * ((1 << k) + 1)) + 1], mat[2 * (l * ((1 << k) + 1))]); };
+  if (k == 1) {
+    const double t0 = arg(0), t1 = arg(1);
+    c += t0;
+    alpha[q[0]] += t1 - t0;
+  } else {
+    // local index l = b0 + 2 b1, b0 = bit of q[0], b1 = bit of q[1]
+    const double t00 = arg(0), t10 = arg(1), t01 = arg(2), t11 = arg(3);
+    c += t00;
+    alpha[q[0]] += t10 - t00;
+    alpha[q[1]] += t01 - t00;
+    const int a = std::min(q[0], q[1]), b = std::max(q[0], q[1]);
+    beta[a][b] += t11 - t10 - t01 + t00;
+  }
+}
+
+void phase_tables(const PhasePoly& p, int n, std::vector<PhaseTables>& out) {
+  out.clear();
+  auto chunk = [](int q) { return q >> 3; };
+  // cross-chunk pairs and a greedy vertex cover (highest remaining degree first)
+  std::vector<std::pair<int, int>> cross;
+  for (int a = 0; a < n; ++a)
+    for (int b = a + 1; b < n; ++b)
+      if (wrap(p.beta[a][b]) != 0.0 && chunk(a) != chunk(b)) cross.push_back({a, b});
+  std::vector<int> owner(cross.size(), -1), hubs;
+  while (true) {
+    std::vector<int> deg(n, 0);
+    for (size_t e = 0; e < cross.size(); ++e)
+      if (owner[e] < 0) {
+        ++deg[cross[e].first];
+        ++deg[cross[e].second];
+      }
+    const int h = (int)(std::max_element(deg.begin(), deg.end()) - deg.begin());
+    if (deg[h] == 0) break;
+    for (size_t e = 0; e < cross.size(); ++e)
+      if (owner[e] < 0 && (cross[e].first == h || cross[e].second == h)) owner[e] = h;
+    hubs.push_back(h);
+  }
+  const size_t npass = std::max<size_t>(1, (hubs.size() + kPhaseHubs - 1) / kPhaseHubs);
+  const double turn = 1.0 / kTwoPi;
+  for (size_t pi = 0; pi < npass; ++pi) {
+    PhaseTables t;
+    t.tab.assign(kPhaseTableFloats, 0.f);
+    std::vector<double> T((size_t)kPhaseChunks * 256, 0.0);
+    std::vector<double> R((size_t)kPhaseHubs * kPhaseChunks * 256, 0.0);
+    if (pi == 0) {
+      // linear and same-chunk quadratic terms, plus the global phase in chunk 0
+      for (int c = 0; c < kPhaseChunks; ++c)
+        for (int v = 0; v < 256; ++v) {
+          double th = c == 0 ? p.c : 0.0;
+          for (int bit = 0; bit < 8; ++bit) {
+            const int a = 8 * c + bit;
+            if (a >= n || !((v >> bit) & 1)) continue;
+            th += p.alpha[a];
+            for (int bit2 = bit + 1; bit2 < 8; ++bit2) {
+              const int b = 8 * c + bit2;
+              if (b < n && ((v >> bit2) & 1)) th += p.beta[a][b];
+            }
+          }
+          T[(size_t)c * 256 + v] = th;
+        }
+    }
+    for (size_t hi = pi * kPhaseHubs; hi < std::min(hubs.size(), (pi + 1) * kPhaseHubs); ++hi) {
+      const int h = hubs[hi];
+      const int slot = (int)(hi - pi * kPhaseHubs);
+      t.hub[slot] = h;
+      t.nhubs = slot + 1;
+      for (size_t e = 0; e < cross.size(); ++e) {
+        if (owner[e] != h) continue;
+        const int other = cross[e].first == h ? cross[e].second : cross[e].first;
+        const double bb = p.beta[std::min(h, other)][std::max(h, other)];
+        const int c = chunk(other), bit = other & 7;
+        for (int v = 0; v < 256; ++v)
+          if ((v >> bit) & 1) R[((size_t)slot * kPhaseChunks + c) * 256 + v] += bb;
+      }
+    }
+    for (size_t i = 0; i < T.size(); ++i) t.tab[i] = (float)(wrap(T[i]) * turn);
+    for (size_t i = 0; i < R.size(); ++i) t.tab[T.size() + i] = (float)(wrap(R[i]) * turn);
+    out.push_back(std::move(t));
+  }
+}
+
+// Greedy max-k fusion in which pure-phase gates do not block one another.
+// Two blocked sets: qubits a dense gate may not touch (every skipped gate)
+// and qubits a phase gate may not touch (skipped dense gates only, since
+// phase gates commute).  A dense seed grows a dense block that also takes the
+// phase gates that fit; a phase seed collects every phase gate it can reach
+// into a phase block (any width).
+void fuse_phase(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>& out, std::vector<int32_t>& block_of) {
+  out.clear();
+  block_of.assign(n, -1);
+  int nq = 1;
+  std::vector<uint64_t> masks(n);
+  std::vector<char> ph(n), consumed(n, 0);
+  for (size_t i = 0; i < n; ++i) {
+    masks[i] = qmask_of(g[i]);
+    ph[i] = is_phase_matrix(g[i].k, g[i].matrix);
+    for (int j = 0; j < g[i].k; ++j) nq = std::max(nq, g[i].qubits[j] + 1);
+  }
+  std::vector<std::vector<int>> dense_blocks;
+  for (size_t seed = 0; seed < n; ++seed) {
+    if (consumed[seed]) continue;
+    std::vector<int> members{(int)seed};
+    consumed[seed] = 1;
+    uint64_t block_dense = 0, block_phase = 0;
+    if (ph[seed]) {
+      for (size_t h = seed + 1; h < n; ++h) {
+        if (consumed[h]) continue;
+        if (ph[h] && (masks[h] & block_phase) == 0) {
+          members.push_back((int)h);
+          consumed[h] = 1;
+        } else if (!ph[h]) {
+          block_phase |= masks[h];
+        }
+      }
+      PhasePoly poly(nq);
+      for (int i : members) poly.add_gate(g[i].k, g[i].qubits, g[i].matrix);
+      // canonical gates: CP(beta) per pair, diag(1, e^{i alpha}) per qubit, global phase on the first
+      const size_t first = out.size();
+      for (int a = 0; a < nq; ++a)
+        for (int b = a + 1; b < nq; ++b) {
+          const double bb = wrap(poly.beta[a][b]);
+          if (bb == 0.0) continue;
+          FusedGate f;
+          f.k = 2;
+          f.q[0] = a;
+          f.q[1] = b;
+          f.mat.assign(32, 0.0);
+          f.mat[0] = f.mat[2 * 5] = f.mat[2 * 10] = 1.0;
+          f.mat[2 * 15] = std::cos(bb);
+          f.mat[2 * 15 + 1] = std::sin(bb);
+          out.push_back(std::move(f));
+        }
+      for (int a = 0; a < nq; ++a) {
+        const double aa = wrap(poly.alpha[a]);
+        if (aa == 0.0) continue;
+        FusedGate f;
+        f.k = 1;
+        f.q[0] = a;
+        f.mat = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0, std::cos(aa), std::sin(aa)};
+        out.push_back(std::move(f));
+      }
+      if (out.size() == first) {  // the block is a global phase only
+        FusedGate f;
+        f.k = 1;
+        f.q[0] = g[seed].qubits[0];
+        f.mat = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0};
+        out.push_back(std::move(f));
+      }
+      const std::complex<double> gp = std::polar(1.0, poly.c);
+      for (size_t e = 0; e < out[first].mat.size(); e += 2) {
+        const std::complex<double> v = std::complex<double>(out[first].mat[e], out[first].mat[e + 1]) * gp;
+        out[first].mat[e] = v.real();
+        out[first].mat[e + 1] = v.imag();
+      }
+      for (int i : members) block_of[i] = (int32_t)first;
+      continue;
+    }
+    uint64_t S = masks[seed];
+    for (size_t h = seed + 1; h < n; ++h) {
+      if (consumed[h]) continue;
+      const uint64_t qh = masks[h];
+      const bool fits = __builtin_popcountll(S | qh) <= max_k;
+      if (ph[h]) {
+        if ((qh & block_phase) == 0 && fits) {
+          S |= qh;
+          members.push_back((int)h);
+          consumed[h] = 1;
+        } else {
+          block_dense |= qh;
+        }
+      } else {
+        if ((qh & block_dense) == 0 && fits) {
+          S |= qh;
+          members.push_back((int)h);
+          consumed[h] = 1;
+        } else {
+          block_dense |= qh;
+          block_phase |= qh;
+        }
+      }
+      if (__builtin_popcountll(S) >= max_k && (S & ~block_dense) == 0 && (S & ~block_phase) == 0) break;
+    }
+    std::vector<FusedGate> one;
+    std::vector<int32_t> tmp;
+    std::vector<std::vector<int>> blocks{members};
+    fuse_blocks(g, n, blocks, one, tmp);
+    for (int i : members) block_of[i] = (int32_t)out.size();
+    out.push_back(std::move(one[0]));
+  }
+}
+
+}  // namespace sv

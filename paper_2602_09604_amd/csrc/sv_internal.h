@@ -31,7 +31,7 @@ struct DeviceError {
 
 // ---------------------------------------------------------------- passes --
 // One in-place sweep of the state by a k-qubit gate.
-enum Variant { V_AUTO = 0, V_REG = 1, V_LDS = 2, V_MFMA = 3 };
+enum Variant { V_AUTO = 0, V_REG = 1, V_LDS = 2, V_MFMA = 3, V_PHASE = 4 };
 
 struct Pass {
   int k = 0;
@@ -44,6 +44,9 @@ struct Pass {
   int tile_bits = 13;                    // LDS: log2 amplitudes per tile
   int reg_iters = 1;                     // REG: groups per thread
   int mfma_cols = 32;                    // MFMA: groups per wavefront tile
+  // phase passes
+  int nhubs = 0;
+  int hub[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 // Launch shape defaults / tuned values.
@@ -84,6 +87,31 @@ int validate_gates(const sv_gate* g, size_t n, int n_qubits);
 void fuse_greedy(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>& out,
                  std::vector<int32_t>& block_of);
 void fuse_none(const sv_gate* g, size_t n, std::vector<FusedGate>& out, std::vector<int32_t>& block_of);
+void fuse_phase(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>& out, std::vector<int32_t>& block_of);
+bool is_phase_matrix(int k, const double* mat);
+
+// Quadratic phase polynomial theta(x) = c + sum_q alpha_q x_q + sum_{a<b} beta_ab x_a x_b
+// (angles in radians) of a run of pure-phase diagonal gates.
+struct PhasePoly {
+  double c = 0.0;
+  std::vector<double> alpha;                    // per qubit
+  std::vector<std::vector<double>> beta;        // beta[a][b], a < b
+  explicit PhasePoly(int n = 0) : alpha(n, 0.0), beta(n, std::vector<double>(n, 0.0)) {}
+  void add_gate(int k, const int* q, const double* mat);
+};
+// Device tables of one phase pass (angles in turns); returns the passes needed
+// (a polynomial whose cross-chunk terms need more than kPhaseHubs hub qubits is
+// split).
+constexpr int kPhaseChunks = 5;  // 8-bit chunks of the index: n <= 40
+constexpr int kPhaseHubs = 8;
+constexpr size_t kPhaseTableFloats = (size_t)kPhaseChunks * 256 + (size_t)kPhaseHubs * kPhaseChunks * 256;
+struct PhaseTables {
+  int nhubs = 0;
+  int hub[kPhaseHubs] = {0};
+  std::vector<float> tab;  // kPhaseTableFloats: T[chunk][256], then R[hub][chunk][256]
+};
+void phase_tables(const PhasePoly& p, int n, std::vector<PhaseTables>& out);
+void launch_phase(int n, void* psi, const unsigned char* data, int nhubs, const int* hubs, hipStream_t st);
 bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int precision,
                   std::vector<FusedGate>& out, std::vector<int32_t>& block_of);
 

@@ -20,13 +20,13 @@ LIB_PATH = os.path.join(_HERE, "libsv.so")
 SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_EUNSUPPORTED, SV_ESTATE = 0, -1, -2, -3, -4, -5
 SV_C64 = 0
 SV_PREC_FP32_VALU, SV_PREC_FP32_MFMA, SV_PREC_BF16X3, SV_PREC_FP16X3 = 0, 1, 2, 3
-SV_FUSE_NONE, SV_FUSE_GREEDY, SV_FUSE_LEARNED = 0, 1, 2
+SV_FUSE_NONE, SV_FUSE_GREEDY, SV_FUSE_LEARNED, SV_FUSE_PHASE = 0, 1, 2, 3
 SV_VARIANT_AUTO, SV_VARIANT_REG, SV_VARIANT_LDS, SV_VARIANT_MFMA = 0, 1, 2, 3
 SV_MAX_K = 6
 SV_COST_FEATURES = 40
 
 PRECISIONS = {"fp32_valu": 0, "fp32_mfma": 1, "bf16x3": 2, "fp16x3": 3}
-FUSIONS = {"none": 0, "greedy": 1, "learned": 2}
+FUSIONS = {"none": 0, "greedy": 1, "learned": 2, "phase": 3}
 VARIANTS = {"auto": 0, "reg": 1, "lds": 2, "mfma": 3}
 
 
@@ -49,7 +49,7 @@ class sv_run_opts(ctypes.Structure):
 class sv_run_stats(ctypes.Structure):
     _fields_ = [("gates_in", ctypes.c_uint64), ("passes", ctypes.c_uint64), ("bytes", ctypes.c_uint64),
                 ("useful_flops", ctypes.c_double), ("fuse_s", ctypes.c_double), ("gpu_s", ctypes.c_double),
-                ("variant_s", ctypes.c_double * 4), ("variant_passes", ctypes.c_uint64 * 4)]
+                ("variant_s", ctypes.c_double * 5), ("variant_passes", ctypes.c_uint64 * 5)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}

@@ -115,10 +115,12 @@ def test_grid34_mirror_returns_to_zero(state34):
     assert abs(norm - 1.0) <= 1e-5  # norm drift
 
 
-@pytest.mark.parametrize("prec", ["fp16x3", "bf16x3"])
-def test_qft32_closed_form_sampled(prec):
+@pytest.mark.parametrize("prec,fusion", [("fp16x3", "greedy"), ("bf16x3", "greedy"), ("fp16x3", "phase"),
+                                         ("bf16x3", "phase"), ("fp32_valu", "phase")])
+def test_qft32_closed_form_sampled(prec, fusion):
     """Config 3: 32-qubit QFT-like circuit from a seeded basis state, fused to
-    k = 5 on split-precision matrix cores, against the closed form."""
+    k = 5 on split-precision matrix cores (and with the controlled phases as
+    phase passes), against the closed form."""
     import torch
     from paper_2602_09604_amd import sv
     n = 32
@@ -126,8 +128,8 @@ def test_qft32_closed_form_sampled(prec):
     st = sv.State(n)
     try:
         st.set_basis(x)
-        stats = st.apply_circuit(C.qft_like_circuit(n), max_k=5, fusion="greedy", precision=prec, stats=True)
-        say(prec, "passes", stats["passes"], "gpu_s", stats["gpu_s"])
+        stats = st.apply_circuit(C.qft_like_circuit(n), max_k=5, fusion=fusion, precision=prec, stats=True)
+        say(prec, fusion, "passes", stats["passes"], "gpu_s", stats["gpu_s"])
         idx = sample_indices(n, 2)
         acc = oracle.CompareAcc()
         acc.add(read_samples(st, idx), oracle.qft_like_amplitudes(n, x, idx))

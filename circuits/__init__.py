@@ -1,8 +1,9 @@
 """Seeded synthetic circuit generators.
 
 This module is the only code shared by the CPU oracle, the tests and the
-benchmark.  It produces gate lists (qubits + dense matrix) and nothing else:
-no gate is ever applied to a state here.
+benchmark.  It produces gate lists (qubits + dense matrix), seeded random
+state vectors and seeded uniforms for sampling, and nothing else: no gate is
+ever applied to a state here.
 
 Conventions (fixed for the whole project):
 
@@ -19,7 +20,7 @@ oracle and the GPU path consume byte-identical circuits.
 from __future__ import annotations
 
 from dataclasses import dataclass
-from typing import List, Sequence, Tuple
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -30,22 +31,44 @@ __all__ = [
     "batched_ansatz", "ansatz_circuit", "mirror_circuit", "random_circuit",
     "grover_circuit", "quantum_volume_circuit", "synthetic_fusion_circuit",
     "to_arrays", "from_arrays", "save_npz", "load_npz", "count_gates",
+    "random_state_c64", "uniforms",
 ]
 
 
 @dataclass(frozen=True)
 class Gate:
-    """A k-qubit gate: local bit j of the matrix index is state bit qubits[j]."""
+    """A k-qubit gate: local bit j of the matrix index is state bit qubits[j].
+
+    ``controls`` (disjoint from ``qubits``) restrict the gate to the basis
+    states whose control bits equal ``control_values`` (all ones when None);
+    ``k`` counts the target qubits only."""
 
     qubits: Tuple[int, ...]
     matrix: np.ndarray
+    controls: Tuple[int, ...] = ()
+    control_values: Optional[Tuple[int, ...]] = None
 
     @property
     def k(self) -> int:
         return len(self.qubits)
 
+    @property
+    def cmask(self) -> int:
+        m = 0
+        for c in self.controls:
+            m |= 1 << c
+        return m
+
+    @property
+    def cval(self) -> int:
+        vals = self.control_values if self.control_values is not None else (1,) * len(self.controls)
+        v = 0
+        for c, b in zip(self.controls, vals):
+            v |= (int(b) & 1) << c
+        return v
+
     def dagger(self) -> "Gate":
-        return Gate(self.qubits, np.ascontiguousarray(self.matrix.conj().T))
+        return Gate(self.qubits, np.ascontiguousarray(self.matrix.conj().T), self.controls, self.control_values)
 
 
 # ---------------------------------------------------------------------------
@@ -225,31 +248,28 @@ def synthetic_fusion_circuit(n: int, n_gates: int, seed: int, q_min: int = 0) ->
     return gates
 
 
-def _mcz_matrix(k: int) -> np.ndarray:
-    m = np.eye(1 << k, dtype=np.complex128)
-    m[-1, -1] = -1.0
-    return m
-
-
 def grover_circuit(n: int, marked: int, iterations: int) -> List[Gate]:
-    """Grover search on n qubits (n <= 6 so the multi-controlled Z is one dense
-    gate): H on all, then ``iterations`` x (oracle: X-conjugated MCZ marking
-    ``marked``; diffusion: H X MCZ X H)."""
-    if n > 6:
-        raise ValueError("grover_circuit builds the multi-controlled Z as one dense gate (n <= 6)")
+    """Grover search on n qubits: H on all, then ``iterations`` x (oracle:
+    X-conjugated multi-controlled Z marking ``marked``; diffusion:
+    H X MCZ X H).  The multi-controlled Z is a Z on qubit n-1 controlled by
+    qubits 0..n-2 (Table 2's multi-controlled Toffoli, with the target's H
+    conjugation folded in)."""
+    if n < 2:
+        raise ValueError("Grover needs n >= 2")
     qs = tuple(range(n))
+    mcz = Gate((n - 1,), Z, tuple(range(n - 1)))
     gates = [Gate((q,), H) for q in qs]
     for _ in range(iterations):
         for q in qs:
             if not (marked >> q) & 1:
                 gates.append(Gate((q,), X))
-        gates.append(Gate(qs, _mcz_matrix(n)))
+        gates.append(mcz)
         for q in qs:
             if not (marked >> q) & 1:
                 gates.append(Gate((q,), X))
         gates += [Gate((q,), H) for q in qs]
         gates += [Gate((q,), X) for q in qs]
-        gates.append(Gate(qs, _mcz_matrix(n)))
+        gates.append(mcz)
         gates += [Gate((q,), X) for q in qs]
         gates += [Gate((q,), H) for q in qs]
     return gates
@@ -293,9 +313,14 @@ def to_arrays(gates: Sequence[Gate]) -> dict:
         qubits[i, : gate.k] = gate.qubits
         offs[i + 1] = offs[i] + (1 << (2 * gate.k))
     mats = np.zeros(int(offs[-1]), dtype=np.complex128)
+    cmask = np.zeros(g, dtype=np.uint64)
+    cval = np.zeros(g, dtype=np.uint64)
     for i, gate in enumerate(gates):
         mats[offs[i]:offs[i + 1]] = np.asarray(gate.matrix, dtype=np.complex128).reshape(-1)
-    return {"k": ks, "qubits": qubits, "mat_off": offs, "mats": mats}
+        if gate.controls:
+            cmask[i] = gate.cmask
+            cval[i] = gate.cval
+    return {"k": ks, "qubits": qubits, "mat_off": offs, "mats": mats, "cmask": cmask, "cval": cval}
 
 
 def from_arrays(a: dict) -> List[Gate]:
@@ -303,7 +328,11 @@ def from_arrays(a: dict) -> List[Gate]:
     for i in range(len(a["k"])):
         k = int(a["k"][i])
         m = np.asarray(a["mats"][a["mat_off"][i]:a["mat_off"][i + 1]]).reshape(1 << k, 1 << k)
-        gates.append(Gate(tuple(int(v) for v in a["qubits"][i, :k]), np.ascontiguousarray(m)))
+        cm = int(a["cmask"][i]) if "cmask" in a else 0
+        cv = int(a["cval"][i]) if "cval" in a else 0
+        ctl = tuple(q for q in range(64) if (cm >> q) & 1)
+        gates.append(Gate(tuple(int(v) for v in a["qubits"][i, :k]), np.ascontiguousarray(m), ctl,
+                          tuple((cv >> q) & 1 for q in ctl) if ctl else None))
     return gates
 
 
@@ -313,4 +342,18 @@ def save_npz(path, gates: Sequence[Gate], **meta) -> None:
 
 def load_npz(path) -> List[Gate]:
     with np.load(path, allow_pickle=False) as f:
-        return from_arrays({k: f[k] for k in ("k", "qubits", "mat_off", "mats")})
+        return from_arrays({k: f[k] for k in ("k", "qubits", "mat_off", "mats", "cmask", "cval") if k in f})
+
+
+def random_state_c64(n: int, seed: int) -> np.ndarray:
+    """A seeded random normalised complex64 state (Gaussian real and
+    imaginary parts, scaled in float64, then rounded to complex64)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    v = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    v /= np.sqrt(np.sum(np.abs(v) ** 2))
+    return v.astype(np.complex64)
+
+
+def uniforms(count: int, seed: int) -> np.ndarray:
+    """Seeded uniforms in [0, 1) (float64) for sampling."""
+    return np.random.Generator(np.random.PCG64(seed)).random(count)

@@ -13,10 +13,13 @@ Contents, each written from the paper's definitions:
 * ``compare``: max |delta|, relative L2, infidelity and norm drift of a
   complex64 state against a complex128 one;
 * ``full_unitary`` / ``brute_force_state``: an independent construction of
-  the whole 2^n x 2^n circuit operator from Kronecker products (Eq. 3) and
-  a bit permutation, for n <= 10;
-* ``ghz_amplitudes``, ``qft_like_amplitudes``: closed forms of the GHZ and
-  swap-free QFT circuits of Sec. VI;
+  the whole 2^n x 2^n circuit operator from Kronecker products (Eq. 3), a
+  bit permutation and, for controlled gates, a diagonal projector, for
+  n <= 10;
+* ``pauli_expectation``, ``marginal_probabilities``, ``sample_indices``:
+  the plain definitions of what the state-reading kernels return;
+* ``ghz_amplitudes``, ``qft_like_amplitudes``, ``grover_amplitudes``: closed
+  forms of the GHZ, swap-free QFT and Grover circuits of Sec. VI;
 * ``mlp``: float64 reference of the fusion cost model's network.
 """
 from __future__ import annotations
@@ -54,7 +57,11 @@ def _load():
         i64p = ctypes.POINTER(ctypes.c_int64)
         lib.orc_apply_gate.argtypes = [dp, ctypes.c_int, ctypes.c_int, i32p, dp]
         lib.orc_apply_gate.restype = ctypes.c_int
-        lib.orc_apply_circuit.argtypes = [dp, ctypes.c_int, ctypes.c_int64, i32p, i32p, i64p, dp]
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        lib.orc_apply_controlled_gate.argtypes = [dp, ctypes.c_int, ctypes.c_int, i32p, dp,
+                                                  ctypes.c_uint64, ctypes.c_uint64]
+        lib.orc_apply_controlled_gate.restype = ctypes.c_int
+        lib.orc_apply_circuit.argtypes = [dp, ctypes.c_int, ctypes.c_int64, i32p, i32p, i64p, dp, u64p, u64p]
         lib.orc_apply_circuit.restype = ctypes.c_int
         lib.orc_init_basis.argtypes = [dp, ctypes.c_int, ctypes.c_uint64]
         lib.orc_norm_sq.argtypes = [dp, ctypes.c_int64]
@@ -79,13 +86,15 @@ def basis_state(n: int, x: int = 0) -> np.ndarray:
     return psi
 
 
-def apply_gate(psi: np.ndarray, n: int, qubits: Sequence[int], matrix: np.ndarray) -> None:
-    """In place: Eq. 4 for one gate."""
+def apply_gate(psi: np.ndarray, n: int, qubits: Sequence[int], matrix: np.ndarray,
+               cmask: int = 0, cval: int = 0) -> None:
+    """In place: Eq. 4 for one gate, acting only where (index & cmask) == cval."""
     assert psi.dtype == np.complex128 and psi.flags.c_contiguous and psi.size == 1 << n
     q = np.ascontiguousarray(qubits, dtype=np.int32)
     u = np.ascontiguousarray(matrix, dtype=np.complex128)
     assert u.shape == (1 << len(q), 1 << len(q))
-    rc = _load().orc_apply_gate(_dp(psi), n, len(q), q.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(u))
+    rc = _load().orc_apply_controlled_gate(_dp(psi), n, len(q), q.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                           _dp(u), cmask, cval)
     if rc != 0:
         raise ValueError("oracle rejected gate %r" % (tuple(qubits),))
 
@@ -104,7 +113,9 @@ def apply_circuit(n: int, gates, init: int = 0, psi: np.ndarray | None = None) -
         a["k"].ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
         np.ascontiguousarray(a["qubits"]).ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
         a["mat_off"].ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-        _dp(mats))
+        _dp(mats),
+        a["cmask"].ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+        a["cval"].ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
     if rc != 0:
         raise ValueError("oracle rejected the circuit")
     return psi
@@ -178,17 +189,75 @@ def embed_gate(n: int, qubits: Sequence[int], matrix: np.ndarray) -> np.ndarray:
     return p.T @ op_low @ p
 
 
+def embed_controlled(n: int, qubits: Sequence[int], matrix: np.ndarray, cmask: int, cval: int) -> np.ndarray:
+    """Controlled operator D E + (I - D): E = embed_gate(...) and D the
+    diagonal projector onto basis states whose control bits equal cval (it
+    commutes with E because controls and targets are disjoint)."""
+    e = embed_gate(n, qubits, matrix)
+    if cmask == 0:
+        return e
+    d = np.array([1.0 if (x & cmask) == cval else 0.0 for x in range(1 << n)])
+    return d[:, None] * e + np.diag(1.0 - d)
+
+
 def full_unitary(n: int, gates) -> np.ndarray:
     if n > 10:
         raise ValueError("brute force is limited to n <= 10")
     u = np.eye(1 << n, dtype=np.complex128)
     for g in gates:
-        u = embed_gate(n, g.qubits, g.matrix) @ u
+        u = embed_controlled(n, g.qubits, g.matrix, getattr(g, "cmask", 0), getattr(g, "cval", 0)) @ u
     return u
 
 
 def brute_force_state(n: int, gates, init: int = 0) -> np.ndarray:
     return full_unitary(n, gates)[:, init].copy()
+
+
+# ---------------------------------------------------------------------------
+# Measurement (the expectation-value kernel of Sec. IV reads the state without
+# writing it back; these are the plain definitions of what such reads return).
+# ---------------------------------------------------------------------------
+_PX = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+_PY = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+_PZ = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+
+
+def pauli_expectation(psi: np.ndarray, n: int, xmask: int, zmask: int) -> complex:
+    """<psi|P|psi> for the Pauli string with X on the qubits of xmask only, Z
+    on those of zmask only and Y on those of both: every letter is applied to
+    a copy of psi as a one-qubit gate (Eq. 4), then the inner product is
+    taken in FP64.  Not normalised by <psi|psi>."""
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    phi = psi.copy()
+    for q in range(n):
+        x, z = (xmask >> q) & 1, (zmask >> q) & 1
+        if x or z:
+            apply_gate(phi, n, (q,), _PY if (x and z) else (_PX if x else _PZ))
+    return complex(np.vdot(psi, phi))
+
+
+def marginal_probabilities(psi: np.ndarray, n: int, qubits: Sequence[int]) -> np.ndarray:
+    """p[o] = sum of |c_i|^2 over the indices i whose bit qubits[j] is bit j
+    of o (Eq. 1's Born weights summed over the unmeasured qubits)."""
+    psi = np.asarray(psi)
+    i = np.arange(1 << n, dtype=np.int64)
+    o = np.zeros(1 << n, dtype=np.int64)
+    for j, q in enumerate(qubits):
+        o |= ((i >> q) & 1) << j
+    w = psi.real.astype(np.float64) ** 2 + psi.imag.astype(np.float64) ** 2
+    return np.bincount(o, weights=w, minlength=1 << len(qubits))
+
+
+def sample_indices(psi: np.ndarray, uniforms: np.ndarray) -> np.ndarray:
+    """Inverse-CDF sampling of basis states from p_i = |c_i|^2 (FP64): for
+    each u in [0, 1) the smallest i with p_0 + ... + p_i > u * sum(p); a
+    value past the end (rounding) takes the last index with p_i > 0."""
+    psi = np.asarray(psi)
+    w = psi.real.astype(np.float64) ** 2 + psi.imag.astype(np.float64) ** 2
+    cdf = np.cumsum(w)
+    idx = np.searchsorted(cdf, np.asarray(uniforms, dtype=np.float64) * cdf[-1], side="right")
+    last = int(np.flatnonzero(w)[-1])
+    return np.minimum(idx, last).astype(np.int64)
 
 
 # ---------------------------------------------------------------------------
@@ -218,3 +287,17 @@ def qft_like_amplitudes(n: int, x: int, idx) -> np.ndarray:
     num = (np.uint64(x) * bit_reverse(y, n)) & mask
     phase = 2.0 * np.pi * num.astype(np.float64) / float(1 << n)
     return np.exp(1j * phase) * 2.0 ** (-n / 2)
+
+
+def grover_amplitudes(n: int, marked: int, iterations: int, idx) -> np.ndarray:
+    """Grover search from |0..0> after H on every qubit and t iterations of
+    (phase flip of |marked>, then I - 2|s><s|): with sin(theta) = 2^(-n/2)
+    the marked amplitude is (-1)^t sin((2t+1) theta) and every other one is
+    (-1)^t cos((2t+1) theta) / sqrt(2^n - 1).  The sign is that of the
+    diffusion written as -(2|s><s| - I), which H X MCZ X H implements."""
+    idx = np.asarray(list(idx) if not isinstance(idx, np.ndarray) else idx, dtype=np.int64)
+    th = np.arcsin(2.0 ** (-n / 2))
+    a = np.sin((2 * iterations + 1) * th)
+    b = np.cos((2 * iterations + 1) * th) / np.sqrt(2.0 ** n - 1)
+    s = (-1.0) ** iterations
+    return np.where(idx == marked, s * a, s * b).astype(np.complex128)

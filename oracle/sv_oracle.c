@@ -9,7 +9,9 @@
  *   - the state is 2^n complex amplitudes, norm sum |c_i|^2 (Sec. II-A, Eq. 1-2);
  *   - a k-qubit gate is a 2^k x 2^k matrix applied by matrix-vector product to
  *     each of the 2^(n-k) groups of amplitudes that agree on all non-target bits
- *     and enumerate the target bits (Sec. II-A, Eq. 4).
+ *     and enumerate the target bits (Sec. II-A, Eq. 4);
+ *   - a controlled gate acts only on the groups whose control bits hold the
+ *     control values (the indicator 1_c of Eq. 4) and leaves the rest alone.
  * Gates are applied one at a time, in order, never fused and never reordered.
  *
  * Layout: psi[2*i] = Re c_i, psi[2*i+1] = Im c_i (IEEE binary64, no fast-math,
@@ -35,13 +37,19 @@ void orc_init_basis(double* psi, int n, uint64_t x) {
   psi[2 * x] = 1.0;
 }
 
-/* Eq. 4: for each group g of the 2^(n-k) groups, gather the 2^k amplitudes
- * whose target bits enumerate l = 0..2^k-1, multiply by U, scatter back. */
-int orc_apply_gate(double* psi, int n, int k, const int32_t* qubits, const double* U) {
+/* Eq. 4 with the control indicator 1_c: for each group g of the 2^(n-k)
+ * groups, gather the 2^k amplitudes whose target bits enumerate
+ * l = 0..2^k-1, multiply by U, scatter back -- but only for groups whose
+ * control bits (cmask) equal cval; every other group is left as it is.
+ * cmask = 0 is the plain gate. */
+int orc_apply_controlled_gate(double* psi, int n, int k, const int32_t* qubits, const double* U,
+                              uint64_t cmask, uint64_t cval) {
   if (k < 1 || k > 10 || k > n || !psi || !qubits || !U) return ORC_EINVAL;
+  if ((cval & ~cmask) != 0 || (n < 64 && (cmask >> n) != 0)) return ORC_EINVAL;
   int sorted[10];
   for (int j = 0; j < k; ++j) {
     if (qubits[j] < 0 || qubits[j] >= n) return ORC_EINVAL;
+    if ((cmask >> qubits[j]) & 1) return ORC_EINVAL; /* a qubit is a control or a target */
     for (int i = 0; i < j; ++i)
       if (qubits[i] == qubits[j]) return ORC_EINVAL;
     sorted[j] = qubits[j];
@@ -73,6 +81,7 @@ int orc_apply_gate(double* psi, int n, int k, const int32_t* qubits, const doubl
         const uint64_t low = base & (((uint64_t)1 << s) - 1);
         base = ((base >> s) << (s + 1)) | low;
       }
+      if ((base & cmask) != cval) continue; /* 1_c = 0: the group is untouched */
       for (int l = 0; l < dim; ++l) {
         vr[l] = psi[2 * (base + off[l])];
         vi[l] = psi[2 * (base + off[l]) + 1];
@@ -95,12 +104,20 @@ int orc_apply_gate(double* psi, int n, int k, const int32_t* qubits, const doubl
   return ORC_OK;
 }
 
+/* Eq. 4 for an uncontrolled gate. */
+int orc_apply_gate(double* psi, int n, int k, const int32_t* qubits, const double* U) {
+  return orc_apply_controlled_gate(psi, n, k, qubits, U, 0, 0);
+}
+
 /* Apply a serialised gate list in order (k[g], qubits[6*g..], matrices at
- * mats + 2*mat_off[g]). */
+ * mats + 2*mat_off[g]; control mask and values cmask[g], cval[g], or no
+ * controls at all when cmask is NULL). */
 int orc_apply_circuit(double* psi, int n, int64_t n_gates, const int32_t* ks,
-                      const int32_t* qubits6, const int64_t* mat_off, const double* mats) {
+                      const int32_t* qubits6, const int64_t* mat_off, const double* mats,
+                      const uint64_t* cmask, const uint64_t* cval) {
   for (int64_t g = 0; g < n_gates; ++g) {
-    int rc = orc_apply_gate(psi, n, ks[g], qubits6 + 6 * g, mats + 2 * mat_off[g]);
+    int rc = orc_apply_controlled_gate(psi, n, ks[g], qubits6 + 6 * g, mats + 2 * mat_off[g],
+                                       cmask ? cmask[g] : 0, cmask ? cval[g] : 0);
     if (rc != ORC_OK) return rc;
   }
   return ORC_OK;

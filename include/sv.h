@@ -94,12 +94,18 @@ extern "C" {
 /* ---- types -------------------------------------------------------------- */
 typedef struct sv_state sv_state; /* opaque handle */
 
-/* One gate: k qubits (qubits[0..k-1], distinct, any order) and its matrix
- * (2*4^k doubles, borrowed for the duration of the call only). */
+/* One gate: k target qubits (qubits[0..k-1], distinct, any order) and its
+ * matrix (2*4^k doubles, borrowed for the duration of the call only).
+ * Controls (Eq. 4's indicator 1_c): the gate acts only on the basis states
+ * whose bits in cmask equal those of cval and leaves every other amplitude
+ * untouched.  cmask = 0 (a zero-initialised struct) is an ordinary gate;
+ * cmask must be disjoint from the targets and cval a subset of cmask. */
 typedef struct {
   int32_t k;
   int32_t qubits[SV_MAX_K];
   const double* matrix;
+  uint64_t cmask;
+  uint64_t cval;
 } sv_gate;
 
 typedef struct {
@@ -116,8 +122,10 @@ typedef struct {
 typedef struct {
   uint64_t gates_in;     /* gates given */
   uint64_t passes;       /* fused passes launched */
-  uint64_t bytes;        /* algorithmic HBM bytes: passes * 16 * 2^n */
-  double useful_flops;   /* sum over passes of 2^(n-k) * 2^k (8*2^k - 2) */
+  uint64_t bytes;        /* algorithmic HBM bytes: 16 * 2^n per pass, 16 * 2^(n-c)
+                            for a controlled pass with c controls */
+  double useful_flops;   /* sum over passes of groups * 2^k (8*2^k - 2), groups =
+                            2^(n-k) (2^(n-k-c) for a controlled pass) */
   double fuse_s;         /* host time in the fusion pass */
   double gpu_s;          /* device time of the passes (HIP events) */
   double variant_s[5];   /* with opts.timing: device time per kernel family: 1 register,
@@ -156,6 +164,16 @@ int sv_num_qubits(const sv_state* s);
  * SV_EINVAL: qubit out of range or repeated, bad k, NULL matrix/qubits. */
 int sv_apply_gate(sv_state* s, const int32_t* qubits, int k, const double* matrix);
 
+/* Controlled gate (Eq. 4 with the indicator 1_c; the paper's controlled-gate
+ * kernel, Sec. IV): apply the k-qubit matrix to the targets only on the
+ * 2^(n-k-nc) groups whose control qubits controls[0..nc-1] hold
+ * control_values[0..nc-1] (each 0 or 1; NULL means all 1), in FP32 on the
+ * handle's stream, touching only those groups' amplitudes.  Controls and
+ * targets are distinct; 0 <= nc and k + nc <= n.  Asynchronous; the matrix
+ * is copied before the call returns.  SV_EINVAL on bad arguments. */
+int sv_apply_controlled_gate(sv_state* s, const int32_t* qubits, int k, const double* matrix, int nc,
+                             const int32_t* controls, const int32_t* control_values);
+
 /* Apply a circuit: validate all gates, fuse them per opts (FP64 on the host),
  * round each fused matrix once to the pass precision, upload every matrix
  * with one host-to-device copy, then launch one in-place pass per fused gate
@@ -164,7 +182,10 @@ int sv_apply_gate(sv_state* s, const int32_t* qubits, int k, const double* matri
  * FP32 baseline: same kernels, one pass per gate.  When stats is not NULL the
  * call waits for the passes and fills it; otherwise it returns once the work
  * is queued.  The result equals applying the gates one at a time in order,
- * up to FP32 (or split-precision) rounding. */
+ * up to FP32 (or split-precision) rounding.  A controlled gate whose targets
+ * and controls together span at most max_k qubits is lifted to a dense gate
+ * on those qubits and fused (not with FUSE_NONE); a wider one is applied as
+ * a controlled pass of its own, in FP32. */
 int sv_apply_circuit(sv_state* s, const sv_gate* gates, size_t n_gates, const sv_run_opts* opts,
                      sv_run_stats* stats);
 
@@ -186,6 +207,30 @@ int sv_fused_free(sv_gate* fused, size_t n, int32_t* block_of_gate);
 /* sum_i |c_i|^2 (Eq. 1), FP32 products accumulated in FP64 through a
  * two-level block reduction.  Synchronises the handle's stream. */
 int sv_norm(sv_state* s, double* norm_sq);
+
+/* Expectation values of Pauli strings (the paper's expectation-value kernel,
+ * Sec. IV: a read of the state that writes nothing back).  Term t is the
+ * string with X on the qubits of xmask[t] only, Z on zmask[t] only and Y on
+ * both; out[t] = <psi|P_t|psi> (real: P_t is Hermitian), not divided by
+ * <psi|psi>.  Products are formed in FP32 from the complex64 amplitudes and
+ * accumulated in FP64.  Terms that share an X/Y part share one sweep of the
+ * state (up to 8 terms per sweep).  Synchronises the handle's stream.
+ * SV_EINVAL: a mask reaches past n, n_terms > 0 with NULL arrays. */
+int sv_expect_pauli(sv_state* s, size_t n_terms, const uint64_t* xmask, const uint64_t* zmask, double* out);
+
+/* Born probabilities of measuring m = n_meas qubits (1 <= m <= 12):
+ * out[o] (2^m doubles) = sum of |c_i|^2 over the indices whose bit
+ * qubits[j] is bit j of o.  Squares in FP32, sums in FP64.  Synchronises. */
+int sv_marginal_probs(sv_state* s, int n_meas, const int32_t* qubits, double* out);
+
+/* Sample basis states from p_i = |c_i|^2 by the inverse CDF: for each
+ * uniforms[j] in [0, 1), out[j] = the smallest i with p_0 + ... + p_i >
+ * uniforms[j] * sum(p) (FP64 prefix sums; a value past the end, from
+ * rounding, takes the last index with p_i > 0).  The caller draws the
+ * uniforms, so the result is reproducible.  The state is not changed.
+ * Synchronises.  SV_EINVAL: a uniform outside [0, 1), NULL arrays, or a
+ * zero state. */
+int sv_sample(sv_state* s, size_t n_shots, const double* uniforms, uint64_t* out);
 
 /* Copy amplitudes [start, start + count) to host memory as complex64
  * (2*count floats, re/im interleaved), in chunks of 2^26 amplitudes.

@@ -2,6 +2,7 @@
 // norm and read-back.  All device work goes to the handle's stream.
 #include <algorithm>
 #include <chrono>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <string>
@@ -26,6 +27,11 @@ struct sv_state {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   std::vector<hipEvent_t> pass_events;  // per-pass timing events (grown on demand)
+  // state-read scratch (expectations, marginals, sampling), grown on demand
+  unsigned char* meas_dev = nullptr;
+  size_t meas_cap = 0;
+  unsigned char* meas_host = nullptr;  // pinned
+  size_t meas_host_cap = 0;
 };
 
 namespace sv {
@@ -72,6 +78,27 @@ static size_t arena_take(sv_state* s, size_t bytes) {
   return off;
 }
 
+// Device and pinned host scratch for state reads; waits for the stream
+// before replacing a buffer that queued work may still use.
+static void meas_reserve(sv_state* s, size_t dev_bytes, size_t host_bytes) {
+  if (dev_bytes > s->meas_cap) {
+    SV_HIP(hipStreamSynchronize(s->stream));
+    if (s->meas_dev) SV_HIP(hipFree(s->meas_dev));
+    s->meas_dev = nullptr;
+    s->meas_cap = 0;
+    SV_HIP(hipMalloc(&s->meas_dev, dev_bytes));
+    s->meas_cap = dev_bytes;
+  }
+  if (host_bytes > s->meas_host_cap) {
+    SV_HIP(hipStreamSynchronize(s->stream));
+    if (s->meas_host) SV_HIP(hipHostFree(s->meas_host));
+    s->meas_host = nullptr;
+    s->meas_host_cap = 0;
+    SV_HIP(hipHostMalloc(&s->meas_host, host_bytes, hipHostMallocDefault));
+    s->meas_host_cap = host_bytes;
+  }
+}
+
 static void drop_graph(sv_state* s) {
   if (s->graph_exec) {
     SV_HIP(hipStreamSynchronize(s->stream));
@@ -80,9 +107,13 @@ static void drop_graph(sv_state* s) {
   }
 }
 
-static double useful_flops(int n, int k) {
-  return std::ldexp(1.0, n - k) * (double)(1 << k) * (8.0 * (1 << k) - 2.0);
+// Flops and algorithmic bytes of one pass; a controlled pass with c controls
+// works on 2^(n-k-c) groups and moves 16 * 2^(n-c) bytes.
+static double useful_flops(int n, const Pass& p) {
+  const int c = __builtin_popcountll(p.cmask);
+  return std::ldexp(1.0, n - p.k - c) * (double)(1 << p.k) * (8.0 * (1 << p.k) - 2.0);
 }
+static uint64_t pass_bytes(int n, const Pass& p) { return (uint64_t)16 << (n - __builtin_popcountll(p.cmask)); }
 
 // Resolve variants, encode all pass data into one staging region, copy it
 // with one host-to-device transfer, and launch the passes (optionally as one
@@ -102,11 +133,11 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
     passes.push_back(p);
   };
   for (size_t i = 0; i < fused.size();) {
-    if ((o.fusion == SV_FUSE_PHASE || o.fusion == SV_FUSE_LEARNED) &&
-        is_phase_matrix(fused[i].k, fused[i].mat.data())) {
+    auto phase_gate = [&](const FusedGate& f) { return !f.cmask && is_phase_matrix(f.k, f.mat.data()); };
+    if ((o.fusion == SV_FUSE_PHASE || o.fusion == SV_FUSE_LEARNED) && phase_gate(fused[i])) {
       PhasePoly poly(s->n);
       size_t j = i;
-      for (; j < fused.size() && is_phase_matrix(fused[j].k, fused[j].mat.data()); ++j)
+      for (; j < fused.size() && phase_gate(fused[j]); ++j)
         poly.add_gate(fused[j].k, fused[j].q, fused[j].mat.data());
       std::vector<PhaseTables> tabs;
       phase_tables(poly, s->n, tabs);
@@ -128,6 +159,18 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
     p.k = fused[i].k;
     std::copy(fused[i].q, fused[i].q + p.k, p.s);
     p.precision = o.precision;
+    p.cmask = fused[i].cmask;
+    p.cval = fused[i].cval;
+    if (p.cmask) {  // controlled passes run on the register kernel family in FP32
+      p.precision = SV_PREC_FP32_VALU;
+      p.variant = V_REG;
+      p.mat_bytes = pass_data_bytes(p);
+      add(p);
+      mats.push_back(fused[i].mat.data());
+      phase_data.emplace_back();
+      ++i;
+      continue;
+    }
     p.variant = choose_variant(s->n, p.k, p.s, o.precision, o.variant);
     const Shape sh = tuned_shape(p.variant, s->n, p.k, p.s, o.precision);
     p.tile_bits = sh.tile_bits;
@@ -189,9 +232,12 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
     SV_HIP(hipEventElapsedTime(&ms, s->ev0, s->ev1));
     stats->gpu_s = ms * 1e-3;
     stats->passes = passes.size();
-    stats->bytes = (uint64_t)passes.size() * ((uint64_t)16 << s->n);
+    stats->bytes = 0;
     double fl = 0.0;
-    for (const Pass& p : passes) fl += useful_flops(s->n, p.k);
+    for (const Pass& p : passes) {
+      stats->bytes += pass_bytes(s->n, p);
+      if (p.variant != V_PHASE) fl += useful_flops(s->n, p);
+    }
     stats->useful_flops = fl;
     if (timing) {
       for (size_t i = 0; i < passes.size(); ++i) {
@@ -227,8 +273,20 @@ static int check_opts(const sv_run_opts& o) {
 }
 
 // Fuse per opts into `fused`.
-int plan_fusion(const sv_gate* g, size_t n, int n_qubits, const sv_run_opts& o, std::vector<FusedGate>& fused,
+int plan_fusion(const sv_gate* g_in, size_t n, int n_qubits, const sv_run_opts& o, std::vector<FusedGate>& fused,
                 std::vector<int32_t>& block_of) {
+  // controlled gates narrow enough to fuse are lifted to dense gates first
+  std::vector<sv_gate> lowered;
+  std::vector<std::vector<double>> store;
+  const sv_gate* g = g_in;
+  if (o.fusion != SV_FUSE_NONE) {
+    bool any = false;
+    for (size_t i = 0; i < n && !any; ++i) any = g_in[i].cmask != 0;
+    if (any) {
+      lower_controlled(g_in, n, o.max_k, lowered, store);
+      g = lowered.data();
+    }
+  }
   if (o.fusion == SV_FUSE_NONE) {
     fuse_none(g, n, fused, block_of);
   } else if (o.fusion == SV_FUSE_PHASE) {
@@ -324,6 +382,8 @@ int sv_free(sv_state* s) {
   if (s->ev0) (void)hipEventDestroy(s->ev0);
   if (s->ev1) (void)hipEventDestroy(s->ev1);
   for (hipEvent_t e : s->pass_events) (void)hipEventDestroy(e);
+  if (s->meas_dev) (void)hipFree(s->meas_dev);
+  if (s->meas_host) (void)hipHostFree(s->meas_host);
   delete s;
   return SV_OK;
 }
@@ -348,6 +408,38 @@ int sv_apply_gate(sv_state* s, const int32_t* qubits, int k, const double* matri
   g.k = k;
   std::copy(qubits, qubits + k, g.qubits);
   g.matrix = matrix;
+  if (int rc = validate_gates(&g, 1, s->n)) return rc;
+  SV_GUARD_BEGIN
+  SV_HIP(hipSetDevice(s->device));
+  std::vector<FusedGate> fused;
+  std::vector<int32_t> block_of;
+  fuse_none(&g, 1, fused, block_of);
+  sv_run_opts o = default_opts();
+  o.fusion = SV_FUSE_NONE;
+  run_passes(s, fused, o, nullptr);
+  return SV_OK;
+  SV_GUARD_END(s)
+}
+
+int sv_apply_controlled_gate(sv_state* s, const int32_t* qubits, int k, const double* matrix, int nc,
+                             const int32_t* controls, const int32_t* control_values) {
+  if (int rc = check_handle(s)) return rc;
+  if (!qubits) return fail(SV_EINVAL, "qubits is NULL");
+  if (k < 1 || k > SV_MAX_K) return fail(SV_EINVAL, "k must be 1..6");
+  if (nc < 0 || nc > s->n || (nc > 0 && !controls)) return fail(SV_EINVAL, "bad control list");
+  sv_gate g{};
+  g.k = k;
+  std::copy(qubits, qubits + k, g.qubits);
+  g.matrix = matrix;
+  for (int j = 0; j < nc; ++j) {
+    const int q = controls[j];
+    if (q < 0 || q >= s->n) return fail(SV_EINVAL, "control " + std::to_string(q) + " out of range");
+    if ((g.cmask >> q) & 1) return fail(SV_EINVAL, "control " + std::to_string(q) + " repeated");
+    const int v = control_values ? control_values[j] : 1;
+    if (v != 0 && v != 1) return fail(SV_EINVAL, "control values must be 0 or 1");
+    g.cmask |= (uint64_t)1 << q;
+    if (v) g.cval |= (uint64_t)1 << q;
+  }
   if (int rc = validate_gates(&g, 1, s->n)) return rc;
   SV_GUARD_BEGIN
   SV_HIP(hipSetDevice(s->device));
@@ -413,6 +505,8 @@ int sv_fuse(const sv_gate* in, size_t n_in, int n_qubits, const sv_run_opts* opt
       g[i] = sv_gate{};
       g[i].k = fused[i].k;
       std::copy(fused[i].q, fused[i].q + fused[i].k, g[i].qubits);
+      g[i].cmask = fused[i].cmask;
+      g[i].cval = fused[i].cval;
       std::memcpy(m + pos, fused[i].mat.data(), sizeof(double) * fused[i].mat.size());
       g[i].matrix = m + pos;
       pos += fused[i].mat.size();
@@ -452,6 +546,121 @@ int sv_norm(sv_state* s, double* norm_sq) {
   SV_HIP(hipMemcpyAsync(s->norm_host, s->norm_dev, sizeof(double), hipMemcpyDeviceToHost, s->stream));
   SV_HIP(hipStreamSynchronize(s->stream));
   *norm_sq = *s->norm_host;
+  return SV_OK;
+  SV_GUARD_END(s)
+}
+
+int sv_expect_pauli(sv_state* s, size_t n_terms, const uint64_t* xmask, const uint64_t* zmask, double* out) {
+  if (int rc = check_handle(s)) return rc;
+  if (n_terms == 0) return SV_OK;
+  if (!xmask || !zmask || !out) return fail(SV_EINVAL, "xmask / zmask / out is NULL");
+  for (size_t t = 0; t < n_terms; ++t)
+    if (s->n < 64 && ((xmask[t] | zmask[t]) >> s->n) != 0)
+      return fail(SV_EINVAL, "term " + std::to_string(t) + ": Pauli mask past qubit n-1");
+  SV_GUARD_BEGIN
+  SV_HIP(hipSetDevice(s->device));
+  // sweeps: terms grouped by their flip mask, at most 8 per sweep, in first-seen order
+  std::vector<uint64_t> sweep_f;
+  std::vector<std::vector<size_t>> sweep_terms;
+  {
+    std::vector<std::pair<uint64_t, size_t>> open;  // flip mask -> sweep being filled
+    for (size_t t = 0; t < n_terms; ++t) {
+      size_t w = SIZE_MAX;
+      for (auto& pr : open)
+        if (pr.first == xmask[t] && sweep_terms[pr.second].size() < 8) w = pr.second;
+      if (w == SIZE_MAX) {
+        w = sweep_f.size();
+        sweep_f.push_back(xmask[t]);
+        sweep_terms.emplace_back();
+        open.push_back({xmask[t], w});
+      }
+      sweep_terms[w].push_back(t);
+    }
+  }
+  const size_t outs = sizeof(double) * 16 * sweep_f.size();
+  meas_reserve(s, pauli_scratch_bytes() + outs, outs);
+  double* scratch = reinterpret_cast<double*>(s->meas_dev);
+  double* res = reinterpret_cast<double*>(s->meas_dev + pauli_scratch_bytes());
+  for (size_t w = 0; w < sweep_f.size(); ++w) {
+    uint64_t z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (size_t j = 0; j < sweep_terms[w].size(); ++j) z[j] = zmask[sweep_terms[w][j]];
+    launch_pauli(s->psi, s->n, sweep_f[w], (int)sweep_terms[w].size(), z, scratch, res + 16 * w, s->stream);
+  }
+  SV_HIP(hipMemcpyAsync(s->meas_host, res, outs, hipMemcpyDeviceToHost, s->stream));
+  SV_HIP(hipStreamSynchronize(s->stream));
+  const double* h = reinterpret_cast<const double*>(s->meas_host);
+  for (size_t w = 0; w < sweep_f.size(); ++w)
+    for (size_t j = 0; j < sweep_terms[w].size(); ++j) {
+      const size_t t = sweep_terms[w][j];
+      const double re = h[16 * w + 2 * j], im = h[16 * w + 2 * j + 1];
+      // P = i^ny X^f Z^z with ny = |f & z| (the Y letters): Re(i^ny (re + i im))
+      switch (__builtin_popcountll(xmask[t] & zmask[t]) & 3) {
+        case 0: out[t] = re; break;
+        case 1: out[t] = -im; break;
+        case 2: out[t] = -re; break;
+        default: out[t] = im; break;
+      }
+    }
+  return SV_OK;
+  SV_GUARD_END(s)
+}
+
+int sv_marginal_probs(sv_state* s, int n_meas, const int32_t* qubits, double* out) {
+  if (int rc = check_handle(s)) return rc;
+  if (!qubits || !out) return fail(SV_EINVAL, "qubits / out is NULL");
+  if (n_meas < 1 || n_meas > marginal_max_qubits() || n_meas > s->n)
+    return fail(SV_EINVAL, "n_meas must be 1..min(10, n)");
+  int q[16];
+  for (int j = 0; j < n_meas; ++j) {
+    q[j] = qubits[j];
+    if (q[j] < 0 || q[j] >= s->n) return fail(SV_EINVAL, "qubit " + std::to_string(q[j]) + " out of range");
+    for (int a = 0; a < j; ++a)
+      if (q[a] == q[j]) return fail(SV_EINVAL, "qubit " + std::to_string(q[j]) + " repeated");
+  }
+  SV_GUARD_BEGIN
+  SV_HIP(hipSetDevice(s->device));
+  const size_t outs = sizeof(double) << n_meas;
+  meas_reserve(s, marginal_scratch_bytes(n_meas) + outs, outs);
+  double* res = reinterpret_cast<double*>(s->meas_dev + marginal_scratch_bytes(n_meas));
+  launch_marginal(s->psi, s->n, n_meas, q, reinterpret_cast<double*>(s->meas_dev), res, s->stream);
+  SV_HIP(hipMemcpyAsync(s->meas_host, res, outs, hipMemcpyDeviceToHost, s->stream));
+  SV_HIP(hipStreamSynchronize(s->stream));
+  std::memcpy(out, s->meas_host, outs);
+  return SV_OK;
+  SV_GUARD_END(s)
+}
+
+int sv_sample(sv_state* s, size_t n_shots, const double* uniforms, uint64_t* out) {
+  if (int rc = check_handle(s)) return rc;
+  if (n_shots == 0) return SV_OK;
+  if (!uniforms || !out) return fail(SV_EINVAL, "uniforms / out is NULL");
+  for (size_t j = 0; j < n_shots; ++j)
+    if (!(uniforms[j] >= 0.0 && uniforms[j] < 1.0))
+      return fail(SV_EINVAL, "uniform " + std::to_string(j) + " outside [0, 1)");
+  SV_GUARD_BEGIN
+  SV_HIP(hipSetDevice(s->device));
+  constexpr size_t kBatch = (size_t)1 << 20;  // shots per upload
+  const size_t batch = std::min(n_shots, kBatch);
+  const size_t sbytes = (sample_scratch_bytes(s->n) + 255) & ~(size_t)255;
+  meas_reserve(s, sbytes + 16 * batch, 16 * batch);
+  double* scratch = reinterpret_cast<double*>(s->meas_dev);
+  double* u_dev = reinterpret_cast<double*>(s->meas_dev + sbytes);
+  uint64_t* o_dev = reinterpret_cast<uint64_t*>(s->meas_dev + sbytes + 8 * batch);
+  double* u_host = reinterpret_cast<double*>(s->meas_host);
+  uint64_t* o_host = reinterpret_cast<uint64_t*>(s->meas_host + 8 * batch);
+  for (size_t done = 0; done < n_shots; done += batch) {
+    const size_t m = std::min(batch, n_shots - done);
+    SV_HIP(hipStreamSynchronize(s->stream));  // the pinned staging is free again
+    std::memcpy(u_host, uniforms + done, 8 * m);
+    SV_HIP(hipMemcpyAsync(u_dev, u_host, 8 * m, hipMemcpyHostToDevice, s->stream));
+    launch_sample(s->psi, s->n, done == 0, u_dev, m, o_dev, scratch, s->stream);
+    SV_HIP(hipMemcpyAsync(o_host, o_dev, 8 * m, hipMemcpyDeviceToHost, s->stream));
+    SV_HIP(hipStreamSynchronize(s->stream));
+    for (size_t j = 0; j < m; ++j) {
+      if (o_host[j] == ~(uint64_t)0) return fail(SV_EINVAL, "cannot sample a zero state");
+      out[done + j] = o_host[j];
+    }
+  }
   return SV_OK;
   SV_GUARD_END(s)
 }

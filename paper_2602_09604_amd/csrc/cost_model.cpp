@@ -116,9 +116,17 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
     for (int j = 0; j < g[i].k; ++j) m |= (uint64_t)1 << g[i].qubits[j];
     return m;
   };
+  // a controlled pass of its own touches 2^-c of the state (c controls)
+  auto ctrl_ns = [&](uint64_t targets, uint64_t cmask) {
+    return pass_ns(targets) * std::ldexp(1.0, -__builtin_popcountll(cmask));
+  };
   auto total = [&](const std::vector<std::vector<int>>& blocks) {
     double t = 0;
     for (auto& b : blocks) {
+      if (b.size() == 1 && g[b[0]].cmask) {
+        t += ctrl_ns(mask_of(b[0]), g[b[0]].cmask);
+        continue;
+      }
       uint64_t m = 0;
       for (int i : b) m |= mask_of(i);
       t += pass_ns(m);
@@ -157,14 +165,14 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
   double t_ph = 0;
   bool in_run = false;
   for (const FusedGate& f : ph) {
-    if (is_phase_matrix(f.k, f.mat.data())) {
+    if (!f.cmask && is_phase_matrix(f.k, f.mat.data())) {
       if (!in_run) t_ph += pass_ns((uint64_t)1 << (n_qubits - 1));
       in_run = true;
     } else {
       in_run = false;
       uint64_t m = 0;
       for (int j = 0; j < f.k; ++j) m |= (uint64_t)1 << f.q[j];
-      t_ph += pass_ns(m);
+      t_ph += f.cmask ? ctrl_ns(m, f.cmask) : pass_ns(m);
     }
   }
   if (t_ph < best_t) {

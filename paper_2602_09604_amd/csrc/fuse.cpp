@@ -13,6 +13,11 @@
 // A joined gate therefore commutes with every skipped gate before it (they
 // share no qubit), so emitting the block at the seed's position and the
 // skipped gates after it preserves the circuit's action.
+//
+// Controlled gates (Eq. 4's indicator 1_c): one whose targets and controls
+// fit in max_k qubits is lifted to a dense gate on their union and fused like
+// any other; a wider one stays a block of its own (a controlled pass) and
+// blocks all of its qubits, controls included, for every other block.
 #include <algorithm>
 #include <complex>
 #include <cstring>
@@ -41,15 +46,62 @@ int validate_gates(const sv_gate* g, size_t n, int n_qubits) {
         if (g[i].qubits[a] == q)
           return fail(SV_EINVAL, "gate " + std::to_string(i) + ": qubit " + std::to_string(q) +
                                      " repeated");
+      if ((g[i].cmask >> q) & 1)
+        return fail(SV_EINVAL, "gate " + std::to_string(i) + ": qubit " + std::to_string(q) +
+                                   " is both a target and a control");
     }
+    const uint64_t cm = g[i].cmask;
+    if (n_qubits < 64 && (cm >> n_qubits) != 0)
+      return fail(SV_EINVAL, "gate " + std::to_string(i) + ": control out of range");
+    if ((g[i].cval & ~cm) != 0)
+      return fail(SV_EINVAL, "gate " + std::to_string(i) + ": control value outside the control mask");
+    if (k + __builtin_popcountll(cm) > n_qubits)
+      return fail(SV_EINVAL, "gate " + std::to_string(i) + ": more targets and controls than qubits");
   }
   return SV_OK;
 }
 
-static uint64_t qmask(const sv_gate& g) {
-  uint64_t m = 0;
-  for (int j = 0; j < g.k; ++j) m |= (uint64_t)1 << g.qubits[j];
-  return m;
+static uint64_t qmask(const sv_gate& g) { return gate_span(g); }
+
+void lower_controlled(const sv_gate* g, size_t n, int max_k, std::vector<sv_gate>& out,
+                      std::vector<std::vector<double>>& store) {
+  out.assign(g, g + n);
+  store.clear();
+  size_t lifted = 0;
+  for (size_t i = 0; i < n; ++i)
+    if (g[i].cmask && g[i].k + __builtin_popcountll(g[i].cmask) <= std::min(max_k, SV_MAX_K)) ++lifted;
+  store.reserve(lifted);
+  for (size_t i = 0; i < n; ++i) {
+    const sv_gate& src = g[i];
+    const int nc = __builtin_popcountll(src.cmask);
+    if (!src.cmask || src.k + nc > std::min(max_k, SV_MAX_K)) continue;
+    // local bits 0..k-1: the targets as given; k..k+nc-1: the controls, ascending
+    sv_gate d{};
+    d.k = src.k + nc;
+    std::copy(src.qubits, src.qubits + src.k, d.qubits);
+    int cv = 0, j = src.k;
+    for (int q = 0; q < 64; ++q)
+      if ((src.cmask >> q) & 1) {
+        if ((src.cval >> q) & 1) cv |= 1 << (j - src.k);
+        d.qubits[j++] = q;
+      }
+    const int dt = 1 << src.k, D = 1 << d.k;
+    std::vector<double> m((size_t)2 * D * D, 0.0);
+    for (int hi = 0; hi < (1 << nc); ++hi)
+      for (int r = 0; r < dt; ++r)
+        for (int c = 0; c < dt; ++c) {
+          const size_t e = (size_t)(hi * dt + r) * D + (hi * dt + c);
+          if (hi == cv) {
+            m[2 * e] = src.matrix[2 * (r * dt + c)];
+            m[2 * e + 1] = src.matrix[2 * (r * dt + c) + 1];
+          } else if (r == c) {
+            m[2 * e] = 1.0;
+          }
+        }
+    store.push_back(std::move(m));
+    d.matrix = store.back().data();
+    out[i] = d;
+  }
 }
 
 // M <- G M, where M is the 2^K x 2^K block matrix (row-major) and G acts on
@@ -87,6 +139,14 @@ static void left_multiply(std::vector<cd>& M, int K, const sv_gate& g, const int
 
 // Build the fused gate of an ordered member list.
 static void build_block(const sv_gate* g, const std::vector<int>& members, FusedGate& out) {
+  if (members.size() == 1 && g[members[0]].cmask) {  // a controlled pass of its own
+    const sv_gate& c = g[members[0]];
+    out.k = c.k;
+    normalise_gate(c.k, c.qubits, c.matrix, out.q, out.mat);
+    out.cmask = c.cmask;
+    out.cval = c.cval;
+    return;
+  }
   uint64_t S = 0;
   for (int i : members) S |= qmask(g[i]);
   int K = 0;
@@ -120,6 +180,8 @@ void fuse_none(const sv_gate* g, size_t n, std::vector<FusedGate>& out, std::vec
     FusedGate f;
     f.k = g[i].k;
     normalise_gate(g[i].k, g[i].qubits, g[i].matrix, f.q, f.mat);
+    f.cmask = g[i].cmask;
+    f.cval = g[i].cval;
     out.push_back(std::move(f));
     block_of[i] = (int32_t)i;
   }
@@ -140,12 +202,17 @@ void greedy_partition_cost(const sv_gate* g, size_t n, int max_k,
     if (consumed[seed]) continue;
     std::vector<int> members{(int)seed};
     consumed[seed] = 1;
+    if (g[seed].cmask) {  // a remaining controlled gate is a block of its own
+      blocks.push_back(std::move(members));
+      continue;
+    }
     uint64_t S = masks[seed], blocked = 0;
     for (size_t h = seed + 1; h < n; ++h) {
       if (consumed[h]) continue;
       const uint64_t qh = masks[h];
       const uint64_t S2 = S | qh;
-      if ((qh & blocked) == 0 && __builtin_popcountll(S2) <= max_k && (!accept || accept(S, S2, qh))) {
+      if (!g[h].cmask && (qh & blocked) == 0 && __builtin_popcountll(S2) <= max_k &&
+          (!accept || accept(S, S2, qh))) {
         S = S2;
         members.push_back((int)h);
         consumed[h] = 1;

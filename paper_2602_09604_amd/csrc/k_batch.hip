@@ -20,6 +20,8 @@
 #include <cstring>
 #include <mutex>
 
+#include <stdexcept>
+
 #include "k_common.h"
 
 namespace sv {
@@ -194,6 +196,9 @@ void batch_run_impl(void* const* psis, const int* ns, const sv_gate* const* circ
     circs[c].pass0 = (int)passes.size();
     circs[c].npass = (int)fused.size();
     for (auto& f : fused) {
+      if (f.cmask)
+        throw std::invalid_argument("sv_batch_run: a controlled gate wider than max_k qubits (targets plus "
+                                    "controls) cannot run in the batched kernel");
       BPass bp{};
       fill_pass(bp, ns[c], f, (uint32_t)(mats.size() / 2));
       passes.push_back(bp);
@@ -394,5 +399,7 @@ extern "C" int sv_batch_run(sv_state* const* states, const sv_gate* const* circu
     return fail(SV_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.err));
   } catch (const std::bad_alloc&) {
     return fail(SV_ENOMEM, "host allocation failed");
+  } catch (const std::invalid_argument& e) {
+    return fail(SV_EINVAL, e.what());
   }
 }

@@ -27,11 +27,7 @@ namespace {
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kUnitTol = 1e-12;
 
-uint64_t qmask_of(const sv_gate& g) {
-  uint64_t m = 0;
-  for (int j = 0; j < g.k; ++j) m |= (uint64_t)1 << g.qubits[j];
-  return m;
-}
+uint64_t qmask_of(const sv_gate& g) { return gate_span(g); }
 
 double wrap(double a) {
   a = std::fmod(a, kTwoPi);
@@ -151,8 +147,9 @@ void fuse_phase(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>& o
   std::vector<char> ph(n), consumed(n, 0);
   for (size_t i = 0; i < n; ++i) {
     masks[i] = qmask_of(g[i]);
-    ph[i] = is_phase_matrix(g[i].k, g[i].matrix);
-    for (int j = 0; j < g[i].k; ++j) nq = std::max(nq, g[i].qubits[j] + 1);
+    ph[i] = !g[i].cmask && is_phase_matrix(g[i].k, g[i].matrix);
+    for (int q = 0; q < 64; ++q)
+      if ((masks[i] >> q) & 1) nq = std::max(nq, q + 1);
   }
   std::vector<std::vector<int>> dense_blocks;
   for (size_t seed = 0; seed < n; ++seed) {
@@ -214,10 +211,10 @@ void fuse_phase(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>& o
       continue;
     }
     uint64_t S = masks[seed];
-    for (size_t h = seed + 1; h < n; ++h) {
+    for (size_t h = seed + 1; h < n && !g[seed].cmask; ++h) {  // a controlled pass stays alone
       if (consumed[h]) continue;
       const uint64_t qh = masks[h];
-      const bool fits = __builtin_popcountll(S | qh) <= max_k;
+      const bool fits = !g[h].cmask && __builtin_popcountll(S | qh) <= max_k;
       if (ph[h]) {
         if ((qh & block_phase) == 0 && fits) {
           S |= qh;

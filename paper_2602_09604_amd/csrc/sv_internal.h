@@ -47,6 +47,9 @@ struct Pass {
   // phase passes
   int nhubs = 0;
   int hub[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // controlled passes: act only where (index & cmask) == cval
+  uint64_t cmask = 0;
+  uint64_t cval = 0;
 };
 
 // Launch shape defaults / tuned values.
@@ -79,10 +82,22 @@ int lds_tile_bits_for(int n, int want);
 
 // Fusion (fuse.cpp).
 struct FusedGate {
-  int k;
-  int q[SV_MAX_K];             // ascending
+  int k = 0;
+  int q[SV_MAX_K] = {0, 0, 0, 0, 0, 0};  // ascending
   std::vector<double> mat;     // 2 * 4^k doubles, row-major, local bit j = q[j]
+  uint64_t cmask = 0;          // controls of a controlled pass (0: none)
+  uint64_t cval = 0;
 };
+// Controlled gates that fit in max_k qubits together with their controls,
+// lifted to dense gates on the union; the others are kept (and later run as
+// controlled passes).  `store` owns the lifted matrices.
+void lower_controlled(const sv_gate* g, size_t n, int max_k, std::vector<sv_gate>& out,
+                      std::vector<std::vector<double>>& store);
+inline uint64_t gate_span(const sv_gate& g) {
+  uint64_t m = g.cmask;
+  for (int j = 0; j < g.k; ++j) m |= (uint64_t)1 << g.qubits[j];
+  return m;
+}
 int validate_gates(const sv_gate* g, size_t n, int n_qubits);
 void fuse_greedy(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>& out,
                  std::vector<int32_t>& block_of);
@@ -112,6 +127,19 @@ struct PhaseTables {
 };
 void phase_tables(const PhasePoly& p, int n, std::vector<PhaseTables>& out);
 void launch_phase(int n, void* psi, const unsigned char* data, int nhubs, const int* hubs, hipStream_t st);
+void launch_ctrl(const Pass& p, int n, void* psi, const float2* U, hipStream_t st);
+
+// State reads (k_measure.hip).
+size_t pauli_scratch_bytes();
+void launch_pauli(const void* psi, int n, uint64_t f, int nt, const uint64_t* z, double* scratch, double* out,
+                  hipStream_t st);
+int marginal_max_qubits();
+size_t marginal_scratch_bytes(int m);
+void launch_marginal(const void* psi, int n, int m, const int* qubits, double* scratch, double* out,
+                     hipStream_t st);
+size_t sample_scratch_bytes(int n);
+void launch_sample(const void* psi, int n, bool prepare, const double* uniforms, uint64_t shots, uint64_t* out,
+                   double* scratch, hipStream_t st);
 bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int precision,
                   std::vector<FusedGate>& out, std::vector<int32_t>& block_of);
 

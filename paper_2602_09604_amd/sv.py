@@ -38,7 +38,8 @@ class SvError(RuntimeError):
 
 class sv_gate(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("qubits", ctypes.c_int32 * SV_MAX_K),
-                ("matrix", ctypes.POINTER(ctypes.c_double))]
+                ("matrix", ctypes.POINTER(ctypes.c_double)), ("cmask", ctypes.c_uint64),
+                ("cval", ctypes.c_uint64)]
 
 
 class sv_run_opts(ctypes.Structure):
@@ -63,6 +64,7 @@ _vp = ctypes.c_void_p
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _dp = ctypes.POINTER(ctypes.c_double)
 _fp = ctypes.POINTER(ctypes.c_float)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
 
 _SIGS = {
     "sv_alloc": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
@@ -70,6 +72,10 @@ _SIGS = {
     "sv_set_basis": (ctypes.c_int, [_vp, ctypes.c_uint64]),
     "sv_num_qubits": (ctypes.c_int, [_vp]),
     "sv_apply_gate": (ctypes.c_int, [_vp, _i32p, ctypes.c_int, _dp]),
+    "sv_apply_controlled_gate": (ctypes.c_int, [_vp, _i32p, ctypes.c_int, _dp, ctypes.c_int, _i32p, _i32p]),
+    "sv_expect_pauli": (ctypes.c_int, [_vp, ctypes.c_size_t, _u64p, _u64p, _dp]),
+    "sv_marginal_probs": (ctypes.c_int, [_vp, ctypes.c_int, _i32p, _dp]),
+    "sv_sample": (ctypes.c_int, [_vp, ctypes.c_size_t, _dp, _u64p]),
     "sv_apply_circuit": (ctypes.c_int, [_vp, ctypes.POINTER(sv_gate), ctypes.c_size_t,
                                         ctypes.POINTER(sv_run_opts), ctypes.POINTER(sv_run_stats)]),
     "sv_fuse": (ctypes.c_int, [ctypes.POINTER(sv_gate), ctypes.c_size_t, ctypes.c_int,
@@ -150,6 +156,9 @@ class GateArray:
             m = np.asarray(g.matrix, dtype=np.complex128).reshape(-1)
             self.mats[pos:pos + m.size] = m
             self.arr[i].matrix = ctypes.cast(base + 16 * pos, _dp)
+            if getattr(g, "controls", ()):
+                self.arr[i].cmask = g.cmask
+                self.arr[i].cval = g.cval
             pos += m.size
 
     @property
@@ -192,6 +201,41 @@ def sv_apply_gate(h: int, qubits: Sequence[int], matrix) -> None:
     _check(lib().sv_apply_gate(_vp(h), q.ctypes.data_as(_i32p), len(q), m.ctypes.data_as(_dp)))
 
 
+def sv_apply_controlled_gate(h: int, qubits: Sequence[int], matrix, controls: Sequence[int],
+                             control_values: Optional[Sequence[int]] = None) -> None:
+    q = np.ascontiguousarray(qubits, dtype=np.int32)
+    m = np.ascontiguousarray(matrix, dtype=np.complex128)
+    c = np.ascontiguousarray(controls, dtype=np.int32)
+    v = None if control_values is None else np.ascontiguousarray(control_values, dtype=np.int32)
+    _check(lib().sv_apply_controlled_gate(_vp(h), q.ctypes.data_as(_i32p), len(q), m.ctypes.data_as(_dp), len(c),
+                                          c.ctypes.data_as(_i32p), None if v is None else v.ctypes.data_as(_i32p)))
+
+
+def sv_expect_pauli(h: int, xmask, zmask) -> np.ndarray:
+    x = np.ascontiguousarray(np.atleast_1d(np.asarray(xmask, dtype=np.uint64)))
+    z = np.ascontiguousarray(np.atleast_1d(np.asarray(zmask, dtype=np.uint64)))
+    if x.shape != z.shape:
+        raise ValueError("xmask and zmask must have the same length")
+    out = np.zeros(x.size, dtype=np.float64)
+    _check(lib().sv_expect_pauli(_vp(h), x.size, x.ctypes.data_as(_u64p), z.ctypes.data_as(_u64p),
+                                 out.ctypes.data_as(_dp)))
+    return out
+
+
+def sv_marginal_probs(h: int, qubits: Sequence[int]) -> np.ndarray:
+    q = np.ascontiguousarray(qubits, dtype=np.int32)
+    out = np.zeros(1 << max(0, len(q)), dtype=np.float64)
+    _check(lib().sv_marginal_probs(_vp(h), len(q), q.ctypes.data_as(_i32p), out.ctypes.data_as(_dp)))
+    return out
+
+
+def sv_sample(h: int, uniforms) -> np.ndarray:
+    u = np.ascontiguousarray(uniforms, dtype=np.float64)
+    out = np.zeros(u.size, dtype=np.uint64)
+    _check(lib().sv_sample(_vp(h), u.size, u.ctypes.data_as(_dp), out.ctypes.data_as(_u64p)))
+    return out
+
+
 def sv_apply_circuit(h: int, gates, opts: Optional[sv_run_opts] = None, want_stats: bool = False) -> Optional[dict]:
     ga = GateArray(gates)
     st = sv_run_stats() if want_stats else None
@@ -216,7 +260,9 @@ def sv_fuse(gates, n_qubits: int, opts: Optional[sv_run_opts] = None):
             k = g.k
             d = 1 << k
             m = np.ctypeslib.as_array(g.matrix, shape=(2 * d * d,)).copy().view(np.complex128).reshape(d, d)
-            fused.append(Gate(tuple(g.qubits[j] for j in range(k)), m))
+            ctl = tuple(q for q in range(64) if (g.cmask >> q) & 1)
+            fused.append(Gate(tuple(g.qubits[j] for j in range(k)), m, ctl,
+                              tuple((g.cval >> q) & 1 for q in ctl) if ctl else None))
         block_of = np.ctypeslib.as_array(blk, shape=(len(gates),)).copy() if len(gates) else np.zeros(0, np.int32)
     finally:
         lib().sv_fused_free(out, n_out.value, blk)
@@ -392,6 +438,18 @@ class State:
 
     def apply_gate(self, qubits, matrix) -> None:
         sv_apply_gate(self.h, qubits, matrix)
+
+    def apply_controlled_gate(self, qubits, matrix, controls, control_values=None) -> None:
+        sv_apply_controlled_gate(self.h, qubits, matrix, controls, control_values)
+
+    def expect_pauli(self, xmask, zmask) -> np.ndarray:
+        return sv_expect_pauli(self.h, xmask, zmask)
+
+    def marginal_probs(self, qubits) -> np.ndarray:
+        return sv_marginal_probs(self.h, qubits)
+
+    def sample(self, uniforms) -> np.ndarray:
+        return sv_sample(self.h, uniforms)
 
     def apply_circuit(self, gates, max_k: int = 4, fusion="greedy", precision="fp32_valu",
                       use_graph: bool = False, variant="auto", stats: bool = False, timing: bool = False):

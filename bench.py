@@ -163,6 +163,70 @@ def batch_figures(max_k: int) -> dict:
             s.free()
 
 
+def other_workloads() -> dict:
+    """The paper's other circuit families at 30-32 qubits and the state
+    reads, each timed on the GPU (device time of the passes; wall time of
+    the synchronous reads)."""
+    import numpy as np
+    import torch
+    import circuits as C
+    from paper_2602_09604_amd import sv
+    out = {}
+    n = 32
+    st = sv.State(n)
+    try:
+        x = C.qft_input_basis(n, 0)
+        qft = C.qft_like_circuit(n)
+        for fusion in ("greedy", "phase"):
+            st.set_basis(x)
+            s = st.apply_circuit(qft, max_k=5, fusion=fusion, precision="fp16x3", stats=True)
+            out["qft32_" + fusion] = {"gates": len(qft), "passes": s["passes"], "gpu_s": s["gpu_s"],
+                                      "gates_per_s_gpu": len(qft) / s["gpu_s"]}
+            log("qft32 %s: %d passes %.3f s" % (fusion, s["passes"], s["gpu_s"]))
+        marked, iters = 0x2D2D2D2D, 3
+        grover = C.grover_circuit(n, marked, iters)
+        st.set_basis(0)
+        s = st.apply_circuit(grover, max_k=6, fusion="greedy", precision="fp16x3", stats=True)
+        out["grover32"] = {"gates": len(grover), "iterations": iters, "passes": s["passes"], "gpu_s": s["gpu_s"],
+                           "gates_per_s_gpu": len(grover) / s["gpu_s"],
+                           "marked_probability": abs(complex(st.read(marked, 1)[0])) ** 2}
+        log("grover32:", out["grover32"])
+        qv = C.quantum_volume_circuit(n, n, seed=0)
+        st.set_basis(0)
+        s = st.apply_circuit(qv, max_k=6, fusion="greedy", precision="fp16x3", stats=True)
+        out["qv32"] = {"gates": len(qv), "depth": n, "passes": s["passes"], "gpu_s": s["gpu_s"],
+                       "gates_per_s_gpu": len(qv) / s["gpu_s"]}
+        log("qv32:", out["qv32"])
+        # state reads on the quantum-volume output
+        state_bytes = 8.0 * (1 << n)
+
+        def timed(fn, reps=3):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            return (time.perf_counter() - t0) / reps
+
+        xm = np.array([0b1011 << 20] * 8, dtype=np.uint64)
+        zm = np.array([(1 << t) | (1 << (t + 9)) for t in range(8)], dtype=np.uint64)
+        t = timed(lambda: st.expect_pauli(xm, zm))
+        out["pauli_8_terms_one_sweep"] = {"s": t, "GBps": state_bytes / t / 1e9}
+        t = timed(lambda: st.expect_pauli(np.zeros(8, np.uint64), zm))
+        out["pauli_8_diagonal_terms"] = {"s": t, "GBps": state_bytes / t / 1e9}
+        t = timed(lambda: st.marginal_probs(tuple(range(0, 30, 3))))
+        out["marginal_10_qubits"] = {"s": t, "GBps": state_bytes / t / 1e9}
+        u = C.uniforms(100000, 0)
+        t = timed(lambda: st.sample(u), reps=2)
+        out["sample_100k_shots"] = {"s": t, "shots_per_s": u.size / t}
+        log("reads:", {k: out[k] for k in out if k.startswith(("pauli", "marginal", "sample"))})
+    finally:
+        st.free()
+        del st
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +243,7 @@ def main():
     ap.add_argument("--no-greedy", action="store_true", help="skip the greedy max-k comparison run")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 512-circuit figures")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-others", action="store_true", help="skip the QFT / Grover / QV / state-read figures")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-step", action="store_true",
                     help="counter-calibration copy + one untimed step, then exit (for rocprofv3 --pmc runs)")
@@ -206,6 +271,17 @@ def main():
         st = sv.State(n)
         s = st.apply_circuit(gates, max_k=args.max_k, fusion="greedy", precision=args.precision, stats=True)
         log("profile step: passes %d gpu %.3f s norm %.9f" % (s["passes"], s["gpu_s"], st.norm()))
+        # the other pass kinds and the state reads, once each on the same state
+        import numpy as np
+        import circuits as C
+        st.apply_controlled_gate((20,), C.X, (n - 1,))                 # touches half the state
+        cps = [C.Gate((a, (a * 7 + 3) % n), C.CP(0.1 * a)) for a in range(n) if a != (a * 7 + 3) % n]
+        st.apply_circuit(cps, max_k=2, fusion="phase")                 # one phase pass
+        st.expect_pauli(np.array([0b101 << 20], np.uint64), np.array([0b11], np.uint64))
+        st.marginal_probs(tuple(range(0, 30, 3)))
+        st.sample(C.uniforms(1000, 0))
+        torch.cuda.synchronize()
+        log("profile step: controlled, phase and read kernels done")
         st.free()
         return
     extra = {}
@@ -298,6 +374,10 @@ def main():
         log("batched 512-circuit workload ...")
         extra["batch512"] = batch_figures(4)
         log("batch:", extra["batch512"])
+
+    if not args.no_others:
+        log("other workloads and state reads ...")
+        extra["other_workloads_32q"] = other_workloads()
 
     cpu = None
     if not args.no_cpu:

@@ -234,7 +234,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="grid34")
     ap.add_argument("--max-k", type=int, default=6)
-    ap.add_argument("--fusion", default="learned", choices=["none", "greedy", "learned"])
+    ap.add_argument("--fusion", default="learned", choices=["none", "greedy", "learned", "block", "phase"])
     ap.add_argument("--precision", default="fp16x3", choices=["fp32_valu", "fp32_mfma", "bf16x3", "fp16x3"])
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (untuned defaults)")
     ap.add_argument("--tune-qubits", type=int, default=28)
@@ -261,7 +261,9 @@ def main():
     if args.profile_step:
         # For hardware-counter runs: a copy of known size (8 GiB read + 8 GiB
         # written) to calibrate the byte counters, then one step of the
-        # circuit (greedy fusion gives the learned search's partition here).
+        # circuit with the largest-block partition (no cost model is trained
+        # here; the per-dispatch bytes of a matrix-core pass do not depend on
+        # which partition produced it).
         a = torch.empty(1 << 30, dtype=torch.complex64, device="cuda")
         b = torch.empty_like(a)
         b.copy_(a)
@@ -269,7 +271,7 @@ def main():
         del a, b
         torch.cuda.empty_cache()
         st = sv.State(n)
-        s = st.apply_circuit(gates, max_k=args.max_k, fusion="greedy", precision=args.precision, stats=True)
+        s = st.apply_circuit(gates, max_k=args.max_k, fusion="block", precision=args.precision, stats=True)
         log("profile step: passes %d gpu %.3f s norm %.9f" % (s["passes"], s["gpu_s"], st.norm()))
         # the other pass kinds and the state reads, once each on the same state
         import numpy as np
@@ -307,8 +309,9 @@ def main():
     sample = 1 << 20
     st = sv.State(n)
     opts = dict(max_k=args.max_k, fusion=args.fusion, precision=args.precision, timing=True)
+    garr = sv.GateArray(gates)  # the circuit as C structs, marshalled once
     for i in range(args.warmup):
-        s, nrm = run_step(st, gates, opts, sample)
+        s, nrm = run_step(st, garr, opts, sample)
         log("warmup %d: passes %d gpu %.3f s norm %.9f" % (i, s["passes"], s["gpu_s"], nrm))
 
     torch.cuda.synchronize()
@@ -316,7 +319,7 @@ def main():
     agg = None
     norms = []
     for i in range(args.steps):
-        s, nrm = run_step(st, gates, opts, sample)
+        s, nrm = run_step(st, garr, opts, sample)
         norms.append(nrm)
         log("step %d: passes %d gpu %.3f s fuse %.3f s" % (i, s["passes"], s["gpu_s"], s["fuse_s"]))
         if agg is None:
@@ -350,12 +353,13 @@ def main():
     })
 
     if not args.no_greedy and args.fusion != "greedy":
-        st.set_basis(0)
-        g = st.apply_circuit(gates, fusion="greedy", max_k=args.max_k, precision=args.precision, stats=True)
-        extra["greedy_max_k"] = {"max_k": args.max_k, "gpu_s": g["gpu_s"], "passes": g["passes"],
-                                 "gates_per_s_gpu": len(gates) / g["gpu_s"]}
-        extra["learned_over_greedy_gpu_time"] = agg["gpu_s"] / args.steps / g["gpu_s"]
-        log("greedy max_k=%d: %.3f s" % (args.max_k, g["gpu_s"]))
+        for mode in ("greedy", "block"):
+            st.set_basis(0)
+            g = st.apply_circuit(garr, fusion=mode, max_k=args.max_k, precision=args.precision, stats=True)
+            extra[mode + "_max_k"] = {"max_k": args.max_k, "gpu_s": g["gpu_s"], "passes": g["passes"],
+                                      "fuse_s": g["fuse_s"], "gates_per_s_gpu": len(gates) / g["gpu_s"]}
+            log("%s max_k=%d: %d passes %.3f s" % (mode, args.max_k, g["passes"], g["gpu_s"]))
+        extra["learned_over_greedy_gpu_time"] = agg["gpu_s"] / args.steps / extra["greedy_max_k"]["gpu_s"]
     if not args.no_plain:
         log("plain unfused FP32 run ...")
         st.set_basis(0)

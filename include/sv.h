@@ -62,9 +62,14 @@ extern "C" {
 /* Fusion policy of sv_apply_circuit / sv_fuse.  NONE applies every gate as
  * its own pass; GREEDY builds blocks of at most max_k qubits (vertical fusion
  * by matrix product, horizontal by tensor product, per-qubit order kept);
- * LEARNED scores candidate partitions with the cost-model network loaded by
- * sv_cost_model_load and keeps the cheapest, falling back to GREEDY when no
- * model is loaded.  PHASE is GREEDY in which pure-phase diagonal gates of at
+ * BLOCK is greedy in passes: each pass takes the set of at most max_k qubits
+ * that absorbs the most remaining gates (grown from every gate of the current
+ * front), which needs far fewer passes than GREEDY on lattice circuits.
+ * LEARNED scores candidate partitions (GREEDY for every k <= max_k,
+ * cost-aware GREEDY variants, BLOCK, PHASE) with the cost-model network
+ * loaded by sv_cost_model_load and keeps the cheapest; with no model loaded
+ * it keeps the candidate with the fewest passes (every pass moves the same
+ * bytes).  PHASE is GREEDY in which pure-phase diagonal gates of at
  * most two qubits (CZ, CP, RZ, Z, S, T, ...) never block one another: those
  * that fit join dense blocks, the others are gathered into phase blocks of
  * any width.  sv_fuse returns a phase block as its canonical diagonal gates
@@ -76,6 +81,7 @@ extern "C" {
 #define SV_FUSE_GREEDY 1
 #define SV_FUSE_LEARNED 2
 #define SV_FUSE_PHASE 3
+#define SV_FUSE_BLOCK 4
 
 /* Kernel variant of a pass (for tests and tuning; AUTO is the default).
  * REG: each lane owns whole groups in registers, gathered straight from HBM

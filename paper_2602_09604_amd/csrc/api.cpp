@@ -262,7 +262,7 @@ static sv_run_opts default_opts() {
 }
 
 static int check_opts(const sv_run_opts& o) {
-  if (o.fusion < SV_FUSE_NONE || o.fusion > SV_FUSE_PHASE) return fail(SV_EINVAL, "opts.fusion invalid");
+  if (o.fusion < SV_FUSE_NONE || o.fusion > SV_FUSE_BLOCK) return fail(SV_EINVAL, "opts.fusion invalid");
   if (o.fusion != SV_FUSE_NONE && (o.max_k < 1 || o.max_k > SV_MAX_K))
     return fail(SV_EINVAL, "opts.max_k must be 1..6");
   if (o.precision < SV_PREC_FP32_VALU || o.precision > SV_PREC_FP16X3)
@@ -292,8 +292,9 @@ int plan_fusion(const sv_gate* g_in, size_t n, int n_qubits, const sv_run_opts& 
   } else if (o.fusion == SV_FUSE_PHASE) {
     fuse_phase(g, n, o.max_k, fused, block_of);
   } else if (o.fusion == SV_FUSE_LEARNED) {
-    if (!fuse_learned(g, n, n_qubits, o.max_k, o.precision, fused, block_of))
-      fuse_greedy(g, n, o.max_k, fused, block_of);
+    fuse_learned(g, n, n_qubits, o.max_k, o.precision, fused, block_of);
+  } else if (o.fusion == SV_FUSE_BLOCK) {
+    fuse_maxblock(g, n, o.max_k, fused, block_of);
   } else {
     fuse_greedy(g, n, o.max_k, fused, block_of);
   }

@@ -1,7 +1,7 @@
 // Learned fusion: the installed MLP predicts the time of one pass from
 // (k, target mask, n, precision); the partition search scores candidate
-// partitions with it and keeps the cheapest.  Without a model, fusion falls
-// back to greedy max-k.
+// partitions with it and keeps the cheapest.  Without a model every pass is
+// priced the same, so the candidate with the fewest passes wins.
 //
 // Prediction target: ln(pass seconds * 1e9 / 2^n), i.e. the log of the pass
 // time per amplitude in nanoseconds, which stays comparable across state
@@ -10,6 +10,7 @@
 // Candidates (Sec. IV-D: the best fusion size depends on circuit and
 // platform, Sec. VII-B picks it by measurement):
 //   - greedy max-k partitions for k = 1 .. max_k;
+//   - largest-block partitions for k = max_k and max_k - 1;
 //   - cost-aware greedy: a gate that would grow a block joins only when the
 //     predicted cost of the larger block does not exceed the smaller block's
 //     cost plus alpha times the cost of running the gate as a pass of its own,
@@ -98,10 +99,13 @@ double cost_model_predict_log(int k, const int* qubits, int n, int precision) {
 
 bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int precision, std::vector<FusedGate>& out,
                   std::vector<int32_t>& block_of) {
-  if (!cost_model_ready()) return false;
+  // Without a model every pass costs the same (it moves the same bytes): the
+  // search then keeps the candidate with the fewest passes.
+  const bool model = cost_model_ready();
   std::unordered_map<uint64_t, double> cache;
   const double amps = std::ldexp(1.0, n_qubits);
   auto pass_ns = [&](uint64_t mask) {
+    if (!model) return 1.0;
     auto it = cache.find(mask);
     if (it != cache.end()) return it->second;
     int q[64], k = 0;
@@ -143,7 +147,17 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
       best = cand;
     }
   }
+  for (int K = max_k; K >= 1 && K >= max_k - 1; --K)  // largest-block partitions
+    for (bool narrow : {false, true}) {
+      maxblock_partition(g, n, K, narrow, cand);
+      const double t = total(cand);
+      if (t < best_t) {
+        best_t = t;
+        best = cand;
+      }
+    }
   for (double alpha : {0.25, 0.5, 1.0}) {
+    if (!model) break;  // the cost-aware variants need predicted times
     greedy_partition_cost(
         g, n, max_k,
         [&](uint64_t S, uint64_t S2, uint64_t qh) {

@@ -22,6 +22,7 @@
 #include <complex>
 #include <cstring>
 #include <functional>
+#include <unordered_map>
 
 #include "sv_internal.h"
 
@@ -228,6 +229,147 @@ void greedy_partition_cost(const sv_gate* g, size_t n, int max_k,
 
 void greedy_partition(const sv_gate* g, size_t n, int max_k, std::vector<std::vector<int>>& blocks) {
   greedy_partition_cost(g, n, max_k, nullptr, blocks);
+}
+
+// Largest-block partition.  Greedy in passes rather than in gates: each pass
+// takes the qubit set S (at most max_k qubits) that absorbs the most gates.
+// A gate is absorbed when its qubits lie in S and no earlier gate left for a
+// later pass shares a qubit with it (the same blocking rule as above, so
+// absorbed gates commute with everything they skip).  Candidate sets grow
+// from each gate of the current front: at every step the qubits of one gate
+// that touches S are added, choosing the addition that absorbs the most gates
+// (fewer qubits on ties), until no addition fits; the best set seen along the
+// way is kept.  Additions come from the outside qubits of gates that touch S
+// (all of them, or with `narrow` only those whose qubits in S are not yet
+// blocked) and from every other gate of the front (horizontal fusion).  A
+// remaining controlled gate is a pass of its own as soon as it reaches the
+// front.
+namespace {
+struct BlockSearch {
+  const sv_gate* g;
+  std::vector<uint64_t> masks;
+  std::vector<int> live;  // indices of gates not yet emitted, in order
+
+  // Gates absorbed by S (indices into g, in order); optionally the candidate
+  // qubit additions seen before S is fully blocked.
+  bool narrow = false;  // additions only from gates whose qubits in S are not yet blocked
+
+  int absorb(uint64_t S, std::vector<int>* got, std::vector<uint64_t>* adds) const {
+    uint64_t blocked = 0;
+    int count = 0;
+    for (int h : live) {
+      const uint64_t qh = masks[h];
+      if ((S & ~blocked) == 0) break;  // every qubit of S is blocked: nothing more can join
+      if ((qh & blocked) == 0 && (qh & ~S) == 0 && !g[h].cmask) {
+        ++count;
+        if (got) got->push_back(h);
+        continue;
+      }
+      if (adds && !g[h].cmask && (qh & S & (narrow ? ~blocked : ~(uint64_t)0)) && (qh & ~S)) adds->push_back(qh & ~S);
+      blocked |= qh;
+    }
+    return count;
+  }
+};
+}  // namespace
+
+void maxblock_partition(const sv_gate* g, size_t n, int max_k, bool narrow, std::vector<std::vector<int>>& blocks) {
+  blocks.clear();
+  BlockSearch b;
+  b.g = g;
+  b.narrow = narrow;
+  b.masks.resize(n);
+  for (size_t i = 0; i < n; ++i) {
+    b.masks[i] = qmask(g[i]);
+    b.live.push_back((int)i);
+  }
+  std::vector<char> done(n, 0);
+  std::vector<uint64_t> adds;
+  while (!b.live.empty()) {
+    // the front: the first remaining gate on each of its qubits
+    std::vector<int> front;
+    uint64_t blocked = 0;
+    for (int h : b.live) {
+      if ((b.masks[h] & blocked) == 0) front.push_back(h);
+      blocked |= b.masks[h];
+    }
+    std::vector<int> chosen;
+    for (int f : front)
+      if (g[f].cmask) {  // a wide controlled gate: its own pass
+        chosen.push_back(f);
+        break;
+      }
+    if (chosen.empty()) {
+      int best_count = -1;
+      uint64_t best_S = 0;
+      std::unordered_map<uint64_t, int> memo;  // absorbed-gate counts of this pass
+      auto count_of = [&](uint64_t S) {
+        auto it = memo.find(S);
+        if (it != memo.end()) return it->second;
+        const int c = b.absorb(S, nullptr, nullptr);
+        memo.emplace(S, c);
+        return c;
+      };
+      for (int f : front) {
+        if (g[f].cmask) continue;
+        uint64_t S = b.masks[f];
+        int seen = count_of(S);
+        uint64_t seen_S = S;
+        while (true) {
+          // additions: the outside qubits of a gate that touches S, or a
+          // whole front gate elsewhere (horizontal fusion)
+          adds.clear();
+          b.absorb(S, nullptr, &adds);
+          for (int f2 : front)
+            if (!g[f2].cmask && (b.masks[f2] & ~S)) adds.push_back(b.masks[f2] & ~S);
+          std::sort(adds.begin(), adds.end());
+          adds.erase(std::unique(adds.begin(), adds.end()), adds.end());
+          int step_count = -1, step_bits = 0;
+          uint64_t step_S = 0;
+          for (uint64_t add : adds) {
+            const uint64_t S2 = S | add;
+            const int bits = __builtin_popcountll(S2);
+            if (bits > max_k) continue;
+            const int c = count_of(S2);
+            if (c > step_count || (c == step_count && bits < step_bits)) {
+              step_count = c;
+              step_bits = bits;
+              step_S = S2;
+            }
+          }
+          if (step_count < 0) break;
+          S = step_S;
+          if (step_count > seen) {
+            seen = step_count;
+            seen_S = S;
+          }
+        }
+        if (seen > best_count) {
+          best_count = seen;
+          best_S = seen_S;
+        }
+      }
+      b.absorb(best_S, &chosen, nullptr);
+    }
+    for (int h : chosen) done[h] = 1;
+    std::vector<int> rest;
+    rest.reserve(b.live.size() - chosen.size());
+    for (int h : b.live)
+      if (!done[h]) rest.push_back(h);
+    b.live.swap(rest);
+    blocks.push_back(std::move(chosen));
+  }
+}
+
+// BLOCK fusion: the two candidate rules of the largest-block search, keeping
+// the partition with fewer passes (the first on ties).
+void fuse_maxblock(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>& out,
+                   std::vector<int32_t>& block_of) {
+  std::vector<std::vector<int>> blocks, other;
+  maxblock_partition(g, n, max_k, false, blocks);
+  maxblock_partition(g, n, max_k, true, other);
+  if (other.size() < blocks.size()) blocks.swap(other);
+  fuse_blocks(g, n, blocks, out, block_of);
 }
 
 void fuse_blocks(const sv_gate* g, size_t n, const std::vector<std::vector<int>>& blocks,

@@ -102,6 +102,11 @@ int validate_gates(const sv_gate* g, size_t n, int n_qubits);
 void fuse_greedy(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>& out,
                  std::vector<int32_t>& block_of);
 void fuse_none(const sv_gate* g, size_t n, std::vector<FusedGate>& out, std::vector<int32_t>& block_of);
+void fuse_maxblock(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>& out,
+                   std::vector<int32_t>& block_of);
+void maxblock_partition(const sv_gate* g, size_t n, int max_k, bool narrow, std::vector<std::vector<int>>& blocks);
+void fuse_blocks(const sv_gate* g, size_t n, const std::vector<std::vector<int>>& blocks,
+                 std::vector<FusedGate>& out, std::vector<int32_t>& block_of);
 void fuse_phase(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>& out, std::vector<int32_t>& block_of);
 bool is_phase_matrix(int k, const double* mat);
 

@@ -26,7 +26,7 @@ SV_MAX_K = 6
 SV_COST_FEATURES = 40
 
 PRECISIONS = {"fp32_valu": 0, "fp32_mfma": 1, "bf16x3": 2, "fp16x3": 3}
-FUSIONS = {"none": 0, "greedy": 1, "learned": 2, "phase": 3}
+FUSIONS = {"none": 0, "greedy": 1, "learned": 2, "phase": 3, "block": 4}
 VARIANTS = {"auto": 0, "reg": 1, "lds": 2, "mfma": 3}
 
 
@@ -237,7 +237,8 @@ def sv_sample(h: int, uniforms) -> np.ndarray:
 
 
 def sv_apply_circuit(h: int, gates, opts: Optional[sv_run_opts] = None, want_stats: bool = False) -> Optional[dict]:
-    ga = GateArray(gates)
+    """`gates`: a list of circuits.Gate, or a GateArray marshalled once beforehand."""
+    ga = gates if isinstance(gates, GateArray) else GateArray(gates)
     st = sv_run_stats() if want_stats else None
     _check(lib().sv_apply_circuit(_vp(h), ga.ptr, ga.n, ctypes.byref(opts) if opts is not None else None,
                                   ctypes.byref(st) if st is not None else None))

@@ -193,3 +193,45 @@ def test_cost_features_layout():
     assert abs(f[0] - 0.5) < 1e-7 and abs(f[1] - 1.0) < 1e-7
     assert f[2 + 0] == 1 and f[2 + 5] == 1 and f[2 + 33] == 1 and f[2:36].sum() == 3
     assert f[36:40].tolist() == [0, 0, 1, 0]
+
+
+@needs_lib
+@pytest.mark.parametrize("max_k", [2, 3, 4, 6])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_block_fusion_equivalent(max_k, seed):
+    n = 9
+    gates = C.random_circuit(n, 60, max_k=min(2, max_k), seed=seed)
+    fused, block_of = sv.sv_fuse(gates, n, sv.make_opts(max_k=max_k, fusion="block"))
+    _check_partition(gates, fused, block_of, max_k)
+    ref = oracle.apply_circuit(n, gates, init=seed)
+    assert np.max(np.abs(oracle.apply_circuit(n, fused, init=seed) - ref)) < 1e-12
+
+
+@needs_lib
+@pytest.mark.parametrize("rows,cols,depth", [(2, 5, 8), (3, 4, 12), (2, 17, 24)])
+def test_block_fusion_fewer_passes_on_lattices(rows, cols, depth):
+    """The largest-block partition needs fewer passes than first-come greedy
+    on grid circuits (the 2x17 depth-24 grid: 53 against 79)."""
+    n = rows * cols
+    gates = C.grid_circuit(rows, cols, depth, seed=0)
+    greedy, _ = sv.sv_fuse(gates, n, sv.make_opts(max_k=6, fusion="greedy"))
+    fused, block_of = sv.sv_fuse(gates, n, sv.make_opts(max_k=6, fusion="block"))
+    _check_partition(gates, fused, block_of, 6)
+    assert len(fused) < len(greedy)
+    if n <= 12:
+        ref = oracle.apply_circuit(n, gates)
+        assert np.max(np.abs(oracle.apply_circuit(n, fused) - ref)) < 1e-12
+    if (rows, cols, depth) == (2, 17, 24):
+        assert len(fused) <= 56, len(fused)
+
+
+@needs_lib
+def test_learned_without_model_keeps_fewest_passes():
+    from paper_2602_09604_amd import costmodel  # noqa: F401  (no model is installed in the CPU suite)
+    gates = C.grid_circuit(3, 4, 12, seed=2)
+    n = 12
+    counts = {f: len(sv.sv_fuse(gates, n, sv.make_opts(max_k=5, fusion=f))[0]) for f in ("greedy", "block", "learned")}
+    assert counts["learned"] <= min(counts["greedy"], counts["block"]), counts
+    fused, _ = sv.sv_fuse(gates, n, sv.make_opts(max_k=5, fusion="learned"))
+    ref = oracle.apply_circuit(n, gates)
+    assert np.max(np.abs(oracle.apply_circuit(n, fused) - ref)) < 1e-12

@@ -35,7 +35,7 @@ def controlled_mix(n, n_gates, seed, max_span=None):
 
 # ------------------------------------------------------------------ host
 @needs_lib
-@pytest.mark.parametrize("fusion", ["none", "greedy", "phase"])
+@pytest.mark.parametrize("fusion", ["none", "greedy", "phase", "block", "learned"])
 @pytest.mark.parametrize("max_k", [2, 4, 6])
 @pytest.mark.parametrize("seed", range(3))
 def test_fusion_with_controls_equivalent(fusion, max_k, seed):
@@ -47,7 +47,7 @@ def test_fusion_with_controls_equivalent(fusion, max_k, seed):
     for f in fused:
         assert f.k <= max(max_k, widest) or fusion == "none"
         if f.controls:  # a kept controlled gate: wider than max_k with its controls, or unfused
-            assert fusion == "none" or f.k + len(f.controls) > max_k
+            assert fusion == "none" or f.k + len(f.controls) > min(max_k, 6)
     init = 3 * seed + 1
     ref = oracle.apply_circuit(n, gates, init=init)
     got = oracle.apply_circuit(n, fused, init=init)
@@ -125,7 +125,8 @@ def test_controlled_gate_kernel_vs_oracle(case):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("fusion,prec", [("none", "fp32_valu"), ("greedy", "fp32_valu"), ("greedy", "fp16x3"),
-                                         ("phase", "fp16x3"), ("greedy", "bf16x3")])
+                                         ("phase", "fp16x3"), ("greedy", "bf16x3"), ("block", "fp16x3"),
+                                         ("block", "fp32_valu")])
 @pytest.mark.parametrize("max_k", [3, 6])
 def test_controlled_circuits_vs_oracle(fusion, prec, max_k):
     n = 18

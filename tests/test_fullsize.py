@@ -73,14 +73,15 @@ def state34():
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("prec", ["fp16x3", "bf16x3", "fp32_valu"])
-def test_grid34_factorised_sampled(state34, prec):
+@pytest.mark.parametrize("prec,fusion", [("fp16x3", "greedy"), ("bf16x3", "greedy"), ("fp32_valu", "greedy"),
+                                         ("fp16x3", "block"), ("fp16x3", "learned")])
+def test_grid34_factorised_sampled(state34, prec, fusion):
     gates = factorised_grid(seed=5)
     psi_l, psi_r = half_states(gates)
     st = state34
     st.set_basis(0)
-    stats = st.apply_circuit(gates, max_k=6, fusion="greedy", precision=prec, stats=True)
-    say(prec, "passes", stats["passes"], "gpu_s", stats["gpu_s"])
+    stats = st.apply_circuit(gates, max_k=6, fusion=fusion, precision=prec, stats=True)
+    say(prec, fusion, "passes", stats["passes"], "gpu_s", stats["gpu_s"])
     idx = sample_indices(N, 1)
     got = read_samples(st, idx)
     ref = product_amplitudes(psi_l, psi_r, idx)

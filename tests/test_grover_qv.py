@@ -16,6 +16,7 @@ pytestmark = pytest.mark.gpu
     (20, 777777, 4, "greedy", "fp16x3"),
     (20, 3, 2, "phase", "fp16x3"),
     (20, 5, 6, "learned", "fp16x3"),
+    (18, 77, 4, "block", "fp32_valu"),
 ])
 def test_grover_full_state_closed_form(n, marked, t, fusion, prec):
     from paper_2602_09604_amd import sv
@@ -52,7 +53,8 @@ def test_grover_28_sampled_and_success_probability():
 
 
 @pytest.mark.parametrize("n,depth,fusion,prec", [(16, 16, "greedy", "fp32_valu"), (20, 20, "learned", "fp16x3"),
-                                                 (20, 12, "none", "fp32_valu"), (22, 10, "greedy", "bf16x3")])
+                                                 (20, 12, "none", "fp32_valu"), (22, 10, "greedy", "bf16x3"),
+                                                 (22, 16, "block", "fp16x3")])
 def test_quantum_volume_vs_oracle(n, depth, fusion, prec):
     from paper_2602_09604_amd import sv
     gates = C.quantum_volume_circuit(n, depth, seed=n + depth)

@@ -277,8 +277,10 @@ inline double a4m(const double* mat, int dk, int row, int col) {
 template <int K, int PREC, int LAYOUT, bool NT>
 void launch_t(const MfmaArgs& a, void* psi, const unsigned char* data, hipStream_t st) {
   const size_t lds = frag_bytes(K, PREC);
+  // 8192 workgroups (32 per CU, four times what can be resident at once):
+  // measured faster than one resident round or than one tile per wave.
   uint64_t blocks = (a.tiles + 3) / 4;
-  if (blocks > 2048) blocks = 2048;
+  if (blocks > 8192) blocks = 8192;
   if constexpr (MfmaPolicy<PREC, LAYOUT>::rolled)
     hipLaunchKernelGGL((k_apply_mfma_rolled<K, PREC, LAYOUT, NT>), dim3((unsigned)blocks), dim3(256), lds, st,
                        (float4*)psi, (const float4*)data, a);

@@ -192,11 +192,12 @@ def other_workloads() -> dict:
                            "marked_probability": abs(complex(st.read(marked, 1)[0])) ** 2}
         log("grover32:", out["grover32"])
         qv = C.quantum_volume_circuit(n, n, seed=0)
-        st.set_basis(0)
-        s = st.apply_circuit(qv, max_k=6, fusion="greedy", precision="fp16x3", stats=True)
-        out["qv32"] = {"gates": len(qv), "depth": n, "passes": s["passes"], "gpu_s": s["gpu_s"],
-                       "gates_per_s_gpu": len(qv) / s["gpu_s"]}
-        log("qv32:", out["qv32"])
+        for fusion in ("greedy", "block"):
+            st.set_basis(0)
+            s = st.apply_circuit(qv, max_k=6, fusion=fusion, precision="fp16x3", stats=True)
+            out["qv32_" + fusion] = {"gates": len(qv), "depth": n, "passes": s["passes"], "gpu_s": s["gpu_s"],
+                                     "gates_per_s_gpu": len(qv) / s["gpu_s"]}
+            log("qv32 %s:" % fusion, out["qv32_" + fusion])
         # state reads on the quantum-volume output
         state_bytes = 8.0 * (1 << n)
 

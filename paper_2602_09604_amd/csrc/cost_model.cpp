@@ -21,6 +21,7 @@
 #include <fstream>
 #include <functional>
 #include <mutex>
+#include <thread>
 #include <unordered_map>
 
 #include "sv_internal.h"
@@ -137,6 +138,30 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
     }
     return t;
   };
+  // The largest-block partitions and the phase partition take longest to
+  // build; they are built on threads while the greedy candidates are scored.
+  std::vector<std::vector<std::vector<int>>> blk;
+  std::vector<std::thread> pool;
+  for (int K = max_k; K >= 1 && K >= max_k - 1; --K)
+    for (bool narrow : {false, true}) blk.push_back({}), pool.emplace_back();
+  {
+    size_t i = 0;
+    for (int K = max_k; K >= 1 && K >= max_k - 1; --K)
+      for (bool narrow : {false, true}) {
+        std::vector<std::vector<int>>* dst = &blk[i];
+        pool[i++] = std::thread([=] { maxblock_partition(g, n, K, narrow, *dst); });
+      }
+  }
+  std::vector<FusedGate> ph;
+  std::vector<int32_t> ph_of;
+  pool.emplace_back([&] { fuse_phase(g, n, max_k, ph, ph_of); });
+  struct Joiner {
+    std::vector<std::thread>& p;
+    ~Joiner() {
+      for (auto& t : p)
+        if (t.joinable()) t.join();
+    }
+  } joiner{pool};
   std::vector<std::vector<int>> best, cand;
   double best_t = 1e300;
   for (int K = 1; K <= max_k; ++K) {
@@ -147,15 +172,6 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
       best = cand;
     }
   }
-  for (int K = max_k; K >= 1 && K >= max_k - 1; --K)  // largest-block partitions
-    for (bool narrow : {false, true}) {
-      maxblock_partition(g, n, K, narrow, cand);
-      const double t = total(cand);
-      if (t < best_t) {
-        best_t = t;
-        best = cand;
-      }
-    }
   for (double alpha : {0.25, 0.5, 1.0}) {
     if (!model) break;  // the cost-aware variants need predicted times
     greedy_partition_cost(
@@ -173,9 +189,14 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
   }
   // The phase-block partition: each run of phase gates is one elementwise
   // sweep, priced as a one-qubit pass on the top qubit (same traffic, no gather).
-  std::vector<FusedGate> ph;
-  std::vector<int32_t> ph_of;
-  fuse_phase(g, n, max_k, ph, ph_of);
+  for (auto& t : pool) t.join();
+  for (auto& b : blk) {  // largest-block partitions, in the order they were started
+    const double t = total(b);
+    if (t < best_t) {
+      best_t = t;
+      best = b;
+    }
+  }
   double t_ph = 0;
   bool in_run = false;
   for (const FusedGate& f : ph) {

@@ -19,16 +19,15 @@
 // any other; a wider one stays a block of its own (a controlled pass) and
 // blocks all of its qubits, controls included, for every other block.
 #include <algorithm>
-#include <complex>
+#include <atomic>
 #include <cstring>
 #include <functional>
+#include <thread>
 #include <unordered_map>
 
 #include "sv_internal.h"
 
 namespace sv {
-
-using cd = std::complex<double>;
 
 int validate_gates(const sv_gate* g, size_t n, int n_qubits) {
   if (n > 0 && !g) return fail(SV_EINVAL, "gates is NULL");
@@ -105,35 +104,48 @@ void lower_controlled(const sv_gate* g, size_t n, int max_k, std::vector<sv_gate
   }
 }
 
-// M <- G M, where M is the 2^K x 2^K block matrix (row-major) and G acts on
-// block-local bits pos[0..k-1] (local bit j of G = block bit pos[j]).
-static void left_multiply(std::vector<cd>& M, int K, const sv_gate& g, const int* pos) {
+// M <- G M, where M is the 2^K x 2^K block matrix (row-major, real and
+// imaginary parts held apart) and G acts on block-local bits pos[0..k-1]
+// (local bit j of G = block bit pos[j]).  The rows of M that differ only in
+// G's bits are combined whole, so the inner loop runs over contiguous columns.
+static void left_multiply(std::vector<double>& Mr, std::vector<double>& Mi, int K, const sv_gate& g,
+                          const int* pos) {
   const int d = 1 << K, k = g.k, dk = 1 << k;
-  std::vector<int> sorted(pos, pos + k);
-  std::sort(sorted.begin(), sorted.end());
-  std::vector<int> off(dk);
+  int sorted[SV_MAX_K];
+  std::copy(pos, pos + k, sorted);
+  std::sort(sorted, sorted + k);
+  int off[1 << SV_MAX_K];
   for (int l = 0; l < dk; ++l) {
     int o = 0;
     for (int j = 0; j < k; ++j)
       if ((l >> j) & 1) o |= 1 << pos[j];
     off[l] = o;
   }
-  std::vector<cd> u(dk * dk);
-  for (int i = 0; i < dk * dk; ++i) u[i] = cd(g.matrix[2 * i], g.matrix[2 * i + 1]);
-  std::vector<cd> v(dk);
+  std::vector<double> tr((size_t)dk * d), ti((size_t)dk * d);
   for (int grp = 0; grp < (d >> k); ++grp) {
     int base = grp;
     for (int j = 0; j < k; ++j) {
       const int lm = (1 << sorted[j]) - 1;
       base = ((base & ~lm) << 1) | (base & lm);
     }
-    for (int col = 0; col < d; ++col) {
-      for (int l = 0; l < dk; ++l) v[l] = M[(size_t)(base + off[l]) * d + col];
-      for (int r = 0; r < dk; ++r) {
-        cd acc = 0.0;
-        for (int c = 0; c < dk; ++c) acc += u[r * dk + c] * v[c];
-        M[(size_t)(base + off[r]) * d + col] = acc;
+    std::fill(tr.begin(), tr.end(), 0.0);
+    std::fill(ti.begin(), ti.end(), 0.0);
+    for (int r = 0; r < dk; ++r) {
+      double* __restrict__ orr = tr.data() + (size_t)r * d;
+      double* __restrict__ ori = ti.data() + (size_t)r * d;
+      for (int c = 0; c < dk; ++c) {
+        const double a = g.matrix[2 * (r * dk + c)], bb = g.matrix[2 * (r * dk + c) + 1];
+        const double* __restrict__ xr = Mr.data() + (size_t)(base + off[c]) * d;
+        const double* __restrict__ xi = Mi.data() + (size_t)(base + off[c]) * d;
+        for (int col = 0; col < d; ++col) {
+          orr[col] += a * xr[col] - bb * xi[col];
+          ori[col] += a * xi[col] + bb * xr[col];
+        }
       }
+    }
+    for (int r = 0; r < dk; ++r) {
+      std::copy(tr.begin() + (size_t)r * d, tr.begin() + (size_t)(r + 1) * d, Mr.begin() + (size_t)(base + off[r]) * d);
+      std::copy(ti.begin() + (size_t)r * d, ti.begin() + (size_t)(r + 1) * d, Mi.begin() + (size_t)(base + off[r]) * d);
     }
   }
 }
@@ -159,17 +171,17 @@ static void build_block(const sv_gate* g, const std::vector<int>& members, Fused
     }
   out.k = K;
   const int d = 1 << K;
-  std::vector<cd> M((size_t)d * d, 0.0);
-  for (int i = 0; i < d; ++i) M[(size_t)i * d + i] = 1.0;
+  std::vector<double> Mr((size_t)d * d, 0.0), Mi((size_t)d * d, 0.0);
+  for (int i = 0; i < d; ++i) Mr[(size_t)i * d + i] = 1.0;
   for (int i : members) {
     int pos[SV_MAX_K];
     for (int j = 0; j < g[i].k; ++j) pos[j] = bitpos[g[i].qubits[j]];
-    left_multiply(M, K, g[i], pos);
+    left_multiply(Mr, Mi, K, g[i], pos);
   }
   out.mat.resize((size_t)2 * d * d);
   for (size_t i = 0; i < (size_t)d * d; ++i) {
-    out.mat[2 * i] = M[i].real();
-    out.mat[2 * i + 1] = M[i].imag();
+    out.mat[2 * i] = Mr[i];
+    out.mat[2 * i + 1] = Mi[i];
   }
 }
 
@@ -377,10 +389,25 @@ void fuse_blocks(const sv_gate* g, size_t n, const std::vector<std::vector<int>>
   out.clear();
   out.resize(blocks.size());
   block_of.assign(n, -1);
-  for (size_t b = 0; b < blocks.size(); ++b) {
-    build_block(g, blocks[b], out[b]);
+  for (size_t b = 0; b < blocks.size(); ++b)
     for (int i : blocks[b]) block_of[i] = (int32_t)b;
+  // The block matrices are independent: build them on host threads when
+  // there are enough of them to pay for the threads.
+  const size_t nb = blocks.size();
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const unsigned nt = (unsigned)std::min<size_t>(hw, nb / 4);
+  if (nt <= 1) {
+    for (size_t b = 0; b < nb; ++b) build_block(g, blocks[b], out[b]);
+    return;
   }
+  std::atomic<size_t> next{0};
+  auto worker = [&] {
+    for (size_t b = next++; b < nb; b = next++) build_block(g, blocks[b], out[b]);
+  };
+  std::vector<std::thread> pool;
+  for (unsigned w = 1; w < nt; ++w) pool.emplace_back(worker);
+  worker();
+  for (auto& t : pool) t.join();
 }
 
 void fuse_greedy(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>& out,

@@ -16,7 +16,10 @@
 // launches of the large circuits.  The LDS-resident size limit is chosen by
 // the autotuner.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <exception>
+#include <thread>
 #include <cstring>
 #include <mutex>
 
@@ -187,10 +190,34 @@ void batch_run_impl(void* const* psis, const int* ns, const sv_gate* const* circ
   std::vector<BPass> passes;
   std::vector<float> mats;  // complex64, interleaved
   int max_levels = 0;
+  // Fusion of independent circuits on host threads (each circuit's plan is
+  // computed by one thread; the assembly below stays in circuit order).
+  std::vector<std::vector<FusedGate>> plans(n_circ);
+  {
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const unsigned nt = (unsigned)std::min<size_t>(hw, std::max<size_t>(1, n_circ / 8));
+    std::atomic<size_t> next{0};
+    std::vector<std::exception_ptr> errs(nt);
+    auto worker = [&](unsigned w) {
+      try {
+        for (size_t c = next++; c < n_circ; c = next++) {
+          std::vector<int32_t> block_of;
+          plan_fusion(circuits[c], n_gates[c], ns[c], o, plans[c], block_of);
+        }
+      } catch (...) {
+        errs[w] = std::current_exception();
+        next = n_circ;
+      }
+    };
+    std::vector<std::thread> pool;
+    for (unsigned w = 1; w < nt; ++w) pool.emplace_back(worker, w);
+    worker(0);
+    for (auto& t : pool) t.join();
+    for (auto& e : errs)
+      if (e) std::rethrow_exception(e);
+  }
   for (size_t c = 0; c < n_circ; ++c) {
-    std::vector<FusedGate> fused;
-    std::vector<int32_t> block_of;
-    plan_fusion(circuits[c], n_gates[c], ns[c], o, fused, block_of);
+    const std::vector<FusedGate>& fused = plans[c];
     circs[c].psi = (float2*)psis[c];
     circs[c].n = ns[c];
     circs[c].pass0 = (int)passes.size();

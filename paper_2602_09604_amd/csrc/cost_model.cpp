@@ -140,21 +140,27 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
   };
   // The largest-block partitions and the phase partition take longest to
   // build; they are built on threads while the greedy candidates are scored.
+  // (Inline, not on threads, when this search already runs on a pool worker.)
+  const bool inline_only = host_pool_worker();
   std::vector<std::vector<std::vector<int>>> blk;
   std::vector<std::thread> pool;
+  auto spawn = [&](std::function<void()> f) {
+    if (inline_only) f();
+    else pool.emplace_back(std::move(f));
+  };
   for (int K = max_k; K >= 1 && K >= max_k - 1; --K)
-    for (bool narrow : {false, true}) blk.push_back({}), pool.emplace_back();
+    for (bool narrow : {false, true}) blk.push_back({});
   {
     size_t i = 0;
     for (int K = max_k; K >= 1 && K >= max_k - 1; --K)
       for (bool narrow : {false, true}) {
-        std::vector<std::vector<int>>* dst = &blk[i];
-        pool[i++] = std::thread([=] { maxblock_partition(g, n, K, narrow, *dst); });
+        std::vector<std::vector<int>>* dst = &blk[i++];
+        spawn([=] { maxblock_partition(g, n, K, narrow, *dst); });
       }
   }
   std::vector<FusedGate> ph;
   std::vector<int32_t> ph_of;
-  pool.emplace_back([&] { fuse_phase(g, n, max_k, ph, ph_of); });
+  spawn([&] { fuse_phase(g, n, max_k, ph, ph_of); });
   struct Joiner {
     std::vector<std::thread>& p;
     ~Joiner() {

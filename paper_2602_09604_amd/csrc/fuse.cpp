@@ -63,6 +63,12 @@ int validate_gates(const sv_gate* g, size_t n, int n_qubits) {
 
 static uint64_t qmask(const sv_gate& g) { return gate_span(g); }
 
+namespace {
+thread_local bool t_pool_worker = false;
+}
+bool host_pool_worker() { return t_pool_worker; }
+void set_host_pool_worker(bool on) { t_pool_worker = on; }
+
 void lower_controlled(const sv_gate* g, size_t n, int max_k, std::vector<sv_gate>& out,
                       std::vector<std::vector<double>>& store) {
   out.assign(g, g + n);
@@ -209,7 +215,8 @@ void greedy_partition_cost(const sv_gate* g, size_t n, int max_k,
                            std::vector<std::vector<int>>& blocks) {
   blocks.clear();
   std::vector<uint64_t> masks(n);
-  for (size_t i = 0; i < n; ++i) masks[i] = qmask(g[i]);
+  uint64_t all = 0;
+  for (size_t i = 0; i < n; ++i) all |= masks[i] = qmask(g[i]);
   std::vector<char> consumed(n, 0);
   for (size_t seed = 0; seed < n; ++seed) {
     if (consumed[seed]) continue;
@@ -232,8 +239,9 @@ void greedy_partition_cost(const sv_gate* g, size_t n, int max_k,
       } else {
         blocked |= qh;
       }
-      // no later gate can join once the block is full and all its qubits are blocked
-      if (__builtin_popcountll(S) >= max_k && (S & ~blocked) == 0) break;
+      // no later gate can join once the block is full and all its qubits are
+      // blocked, or once every qubit of the circuit is blocked
+      if ((__builtin_popcountll(S) >= max_k && (S & ~blocked) == 0) || (all & ~blocked) == 0) break;
     }
     blocks.push_back(std::move(members));
   }
@@ -392,10 +400,17 @@ void fuse_blocks(const sv_gate* g, size_t n, const std::vector<std::vector<int>>
   for (size_t b = 0; b < blocks.size(); ++b)
     for (int i : blocks[b]) block_of[i] = (int32_t)b;
   // The block matrices are independent: build them on host threads when
-  // there are enough of them to pay for the threads.
+  // there is enough work to pay for the threads (many large blocks), and
+  // never from inside another pool's worker.
   const size_t nb = blocks.size();
+  size_t work = 0;  // gate products times block dimension squared
+  for (size_t b = 0; b < nb; ++b) {
+    uint64_t S = 0;
+    for (int i : blocks[b]) S |= qmask(g[i]);
+    work += blocks[b].size() << (2 * __builtin_popcountll(S));
+  }
   const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  const unsigned nt = (unsigned)std::min<size_t>(hw, nb / 4);
+  const unsigned nt = host_pool_worker() || work < ((size_t)1 << 20) ? 1u : (unsigned)std::min<size_t>(hw, nb / 4);
   if (nt <= 1) {
     for (size_t b = 0; b < nb; ++b) build_block(g, blocks[b], out[b]);
     return;

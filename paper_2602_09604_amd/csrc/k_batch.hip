@@ -199,6 +199,10 @@ void batch_run_impl(void* const* psis, const int* ns, const sv_gate* const* circ
     std::atomic<size_t> next{0};
     std::vector<std::exception_ptr> errs(nt);
     auto worker = [&](unsigned w) {
+      set_host_pool_worker(true);
+      struct Reset {
+        ~Reset() { set_host_pool_worker(false); }
+      } reset;
       try {
         for (size_t c = next++; c < n_circ; c = next++) {
           std::vector<int32_t> block_of;

@@ -107,6 +107,10 @@ void fuse_maxblock(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>
 void maxblock_partition(const sv_gate* g, size_t n, int max_k, bool narrow, std::vector<std::vector<int>>& blocks);
 void fuse_blocks(const sv_gate* g, size_t n, const std::vector<std::vector<int>>& blocks,
                  std::vector<FusedGate>& out, std::vector<int32_t>& block_of);
+// Set on threads of a host worker pool so that the work they call does not
+// start threads of its own.
+bool host_pool_worker();
+void set_host_pool_worker(bool on);
 void fuse_phase(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>& out, std::vector<int32_t>& block_of);
 bool is_phase_matrix(int k, const double* mat);
 

@@ -224,6 +224,21 @@ def test_mfma_single_gate(prec, k, tname):
     check(got, oracle.apply_circuit(n, gates))
 
 
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3", "fp32_mfma"])
+@pytest.mark.parametrize("qs", [(2, 9, 14, 19, 23, 25), (0, 3, 9, 14, 20, 25), (1, 2, 9, 14, 20, 25),
+                                (0, 1, 7, 12, 18, 24), (25, 3, 5, 8, 13, 17), (4, 2, 16, 0, 11)])
+def test_mfma_low_target_streaming(prec, qs):
+    """26 qubits (non-temporal streaming on): a target in bits 1..3 is moved to
+    the lane-half bit of the split-precision layout; two such targets keep
+    cached loads; bit 0 targets use the other layout."""
+    n = 26
+    rng = np.random.Generator(np.random.PCG64(sum(qs)))
+    gates = [C.Gate((q,), C.haar_unitary(1, rng)) for q in range(n)] + [C.Gate(qs, C.haar_unitary(len(qs), rng))]
+    say("mfma low target", prec, qs)
+    got = run_gpu(n, gates, fusion="none", precision=prec, variant="mfma")
+    check(got, oracle.apply_circuit(n, gates))
+
+
 @pytest.mark.parametrize("prec", ["fp32_mfma", "bf16x3", "fp16x3"])
 @pytest.mark.parametrize("max_k", [4, 5, 6])
 def test_grid_fused_mfma(prec, max_k):

@@ -171,7 +171,7 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
       ++i;
       continue;
     }
-    p.variant = choose_variant(s->n, p.k, p.s, o.precision, o.variant);
+    p.variant = choose_variant(s->n, p.k, p.s, o.precision, o.variant == SV_VARIANT_SHFL ? V_SHFL : o.variant);
     const Shape sh = tuned_shape(p.variant, s->n, p.k, p.s, o.precision);
     p.tile_bits = sh.tile_bits;
     p.reg_iters = sh.reg_iters;
@@ -243,7 +243,7 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
       for (size_t i = 0; i < passes.size(); ++i) {
         float pm = 0.f;
         SV_HIP(hipEventElapsedTime(&pm, s->pass_events[i], s->pass_events[i + 1]));
-        const int v = passes[i].variant;
+        const int v = variant_family(passes[i].variant);
         stats->variant_s[v] += pm * 1e-3;
         stats->variant_passes[v] += 1;
       }
@@ -267,7 +267,7 @@ static int check_opts(const sv_run_opts& o) {
     return fail(SV_EINVAL, "opts.max_k must be 1..6");
   if (o.precision < SV_PREC_FP32_VALU || o.precision > SV_PREC_FP16X3)
     return fail(SV_EINVAL, "opts.precision invalid");
-  if (o.variant < SV_VARIANT_AUTO || o.variant > SV_VARIANT_MFMA) return fail(SV_EINVAL, "opts.variant invalid");
+  if (o.variant < SV_VARIANT_AUTO || o.variant > SV_VARIANT_SHFL) return fail(SV_EINVAL, "opts.variant invalid");
   if (o.timing != 0 && o.timing != 1) return fail(SV_EINVAL, "opts.timing must be 0 or 1");
   return SV_OK;
 }

@@ -115,6 +115,8 @@ void launch_pass(const Pass& p, int n, void* psi, const unsigned char* arena_dev
   const unsigned char* data = arena_dev + p.mat_off;
   if (p.cmask) {
     launch_ctrl(p, n, psi, reinterpret_cast<const float2*>(data), st);
+  } else if (p.variant == V_SHFL) {
+    launch_shfl(p, n, psi, reinterpret_cast<const float2*>(data), st);
   } else if (p.variant == V_PHASE) {
     launch_phase(n, psi, data, p.nhubs, p.hub, st);
   } else if (p.variant == V_MFMA) {

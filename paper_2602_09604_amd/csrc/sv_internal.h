@@ -31,7 +31,10 @@ struct DeviceError {
 
 // ---------------------------------------------------------------- passes --
 // One in-place sweep of the state by a k-qubit gate.
-enum Variant { V_AUTO = 0, V_REG = 1, V_LDS = 2, V_MFMA = 3, V_PHASE = 4 };
+enum Variant { V_AUTO = 0, V_REG = 1, V_LDS = 2, V_MFMA = 3, V_PHASE = 4, V_SHFL = 5 };
+// Kernel family of a variant in sv_run_stats (the shuffle kernel keeps whole
+// groups in registers: family 1 with the register kernel).
+inline int variant_family(int v) { return v == V_SHFL ? V_REG : v; }
 
 struct Pass {
   int k = 0;
@@ -137,6 +140,8 @@ struct PhaseTables {
 void phase_tables(const PhasePoly& p, int n, std::vector<PhaseTables>& out);
 void launch_phase(int n, void* psi, const unsigned char* data, int nhubs, const int* hubs, hipStream_t st);
 void launch_ctrl(const Pass& p, int n, void* psi, const float2* U, hipStream_t st);
+bool shfl_eligible(int n, int k, const int* s);
+void launch_shfl(const Pass& p, int n, void* psi, const float2* U, hipStream_t st);
 
 // State reads (k_measure.hip).
 size_t pauli_scratch_bytes();

@@ -132,6 +132,7 @@ int sv_autotune(sv_state* s, int budget_ms) {
             std::sort(p.s, p.s + k);
             std::vector<std::pair<int, int>> cands = {{V_REG, 12}, {V_LDS, 10}, {V_LDS, 12}};
             if (mfma_supported(k, prec) && n >= k + 6) cands.push_back({V_MFMA, 12});
+            if (shfl_eligible(n, k, p.s)) cands.push_back({V_SHFL, 12});
             Choice best{V_REG, 12, 1e30};
             for (auto& cand : cands) {
               p.variant = cand.first;
@@ -292,7 +293,7 @@ int sv_tune_load(const char* path) {
     if (std::sscanf(text.c_str() + open, "[%d, %d, %d, %d, %d, %d, %lf]", &p, &k, &q0, &nlow, &var, &tb, &ms) != 7)
       return fail(SV_EINVAL, "malformed tuning entry");
     if (p < 0 || p > 3 || k < 1 || k > SV_MAX_K || q0 < 0 || q0 > 1 || nlow < 0 || nlow > 6 || var < V_REG ||
-        var > V_MFMA || (tb != 10 && tb != 12))
+        var > V_SHFL || var == V_PHASE || (tb != 10 && tb != 12))
       return fail(SV_EINVAL, "tuning entry out of range");
     parsed[Key{p, k, q0, nlow}] = Choice{var, tb, ms};
     pos = close + 1;

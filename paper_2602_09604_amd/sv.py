@@ -27,7 +27,7 @@ SV_COST_FEATURES = 40
 
 PRECISIONS = {"fp32_valu": 0, "fp32_mfma": 1, "bf16x3": 2, "fp16x3": 3}
 FUSIONS = {"none": 0, "greedy": 1, "learned": 2, "phase": 3, "block": 4}
-VARIANTS = {"auto": 0, "reg": 1, "lds": 2, "mfma": 3}
+VARIANTS = {"auto": 0, "reg": 1, "lds": 2, "mfma": 3, "shfl": 4}
 
 
 class SvError(RuntimeError):

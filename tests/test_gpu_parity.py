@@ -62,7 +62,7 @@ TARGET_SETS = {
 }
 
 
-@pytest.mark.parametrize("variant", ["reg", "lds", "auto"])
+@pytest.mark.parametrize("variant", ["reg", "lds", "auto", "shfl"])
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("tname", list(TARGET_SETS))
 def test_single_gate_variants(variant, k, tname):
@@ -222,6 +222,36 @@ def test_mfma_single_gate(prec, k, tname):
     say("mfma single gate", prec, k, tname, qs)
     got = run_gpu(n, gates, fusion="none", precision=prec, variant="mfma")
     check(got, oracle.apply_circuit(n, gates))
+
+
+SHFL_TARGETS = ([(t,) for t in range(1, 7)] + [(0, t) for t in range(1, 7)] + [(t, 0) for t in (3, 6)]
+                + [(a, b) for a in range(1, 7) for b in range(a + 1, 7)] + [(6, 2), (5, 1)])
+
+
+@pytest.mark.parametrize("n", [9, 12])
+@pytest.mark.parametrize("qs", SHFL_TARGETS)
+def test_shuffle_kernel_all_lane_targets(n, qs):
+    """Targets in bits 0..6 (k <= 2, at most two lane targets): partners by
+    cross-lane permutes; the smallest state it runs on is 9 qubits."""
+    sv = _sv()
+    rng = np.random.Generator(np.random.PCG64(n * 100 + sum(qs) * 7 + qs[0]))
+    gates = [C.Gate((q,), C.haar_unitary(1, rng)) for q in range(n)] + [C.Gate(qs, C.haar_unitary(len(qs), rng))]
+    st = sv.State(n)
+    try:
+        st.apply_circuit(gates[:n], fusion="none")
+        s = st.apply_circuit(gates[n:], fusion="none", variant="shfl", timing=True)
+        assert s["variant_passes"][1] == 1
+        check(st.read(), oracle.apply_circuit(n, gates))
+    finally:
+        st.free()
+
+
+@pytest.mark.parametrize("qs", [(1,), (6,), (0, 4), (2, 5), (1, 6)])
+def test_shuffle_kernel_streaming(qs):
+    n = 26  # non-temporal loads and stores
+    rng = np.random.Generator(np.random.PCG64(sum(qs) + 5))
+    gates = [C.Gate((q,), C.haar_unitary(1, rng)) for q in range(n)] + [C.Gate(qs, C.haar_unitary(len(qs), rng))]
+    check(run_gpu(n, gates, fusion="none", variant="shfl"), oracle.apply_circuit(n, gates))
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp16x3", "fp32_mfma"])

@@ -95,6 +95,18 @@ def cpu_baseline(seconds_hint: float = 20.0) -> dict:
     oracle.apply_circuit(n, gates[:count])
     dt = time.perf_counter() - t0
     gps_24 = count / dt
+    # the other workloads, a few seconds each: the QFT-like circuit at 22
+    # qubits (scaled to 32 by 2^-10) and the first 16 batched circuits
+    qn = 22
+    qft = C.qft_like_circuit(qn)
+    t0 = time.perf_counter()
+    oracle.apply_circuit(qn, qft, init=C.qft_input_basis(qn, 0))
+    qdt = time.perf_counter() - t0
+    ns, circs = C.batched_ansatz(512, seed=0)
+    t0 = time.perf_counter()
+    for nb, cb in list(zip(ns, circs))[:16]:
+        oracle.apply_circuit(nb, cb)
+    bdt = time.perf_counter() - t0
     return {
         "value": gps_24 * 2.0 ** (24 - 34),
         "unit": "gates/s",
@@ -102,6 +114,10 @@ def cpu_baseline(seconds_hint: float = 20.0) -> dict:
         "kind": "oracle",
         "sample": "first %d gates of a 24-qubit 2x12 grid circuit (depth 24) in %.1f s = %.3g gates/s at 24 "
                   "qubits, scaled by 2^-10 to the 34-qubit state" % (count, dt, gps_24),
+        "qft32_gates_per_s": len(qft) / qdt * 2.0 ** (qn - 32),
+        "qft_sample": "22-qubit QFT-like circuit (%d gates) in %.2f s, scaled by 2^-10 to 32 qubits" % (len(qft), qdt),
+        "batch_circuits_per_s": 16 / bdt,
+        "batch_sample": "the first 16 of the 512 batched circuits in %.2f s" % bdt,
     }
 
 
@@ -181,7 +197,8 @@ def other_workloads() -> dict:
             st.set_basis(x)
             s = st.apply_circuit(qft, max_k=5, fusion=fusion, precision="fp16x3", stats=True)
             out["qft32_" + fusion] = {"gates": len(qft), "passes": s["passes"], "gpu_s": s["gpu_s"],
-                                      "gates_per_s_gpu": len(qft) / s["gpu_s"]}
+                                      "gates_per_s_gpu": len(qft) / s["gpu_s"],
+                                      "alg_hbm_frac": s["bytes"] / s["gpu_s"] / 1e9 / HBM_PEAK_GBPS}
             log("qft32 %s: %d passes %.3f s" % (fusion, s["passes"], s["gpu_s"]))
         marked, iters = 0x2D2D2D2D, 3
         grover = C.grover_circuit(n, marked, iters)
@@ -189,6 +206,7 @@ def other_workloads() -> dict:
         s = st.apply_circuit(grover, max_k=6, fusion="greedy", precision="fp16x3", stats=True)
         out["grover32"] = {"gates": len(grover), "iterations": iters, "passes": s["passes"], "gpu_s": s["gpu_s"],
                            "gates_per_s_gpu": len(grover) / s["gpu_s"],
+                           "alg_hbm_frac": s["bytes"] / s["gpu_s"] / 1e9 / HBM_PEAK_GBPS,
                            "marked_probability": abs(complex(st.read(marked, 1)[0])) ** 2}
         log("grover32:", out["grover32"])
         qv = C.quantum_volume_circuit(n, n, seed=0)
@@ -196,7 +214,8 @@ def other_workloads() -> dict:
             st.set_basis(0)
             s = st.apply_circuit(qv, max_k=6, fusion=fusion, precision="fp16x3", stats=True)
             out["qv32_" + fusion] = {"gates": len(qv), "depth": n, "passes": s["passes"], "gpu_s": s["gpu_s"],
-                                     "gates_per_s_gpu": len(qv) / s["gpu_s"]}
+                                     "gates_per_s_gpu": len(qv) / s["gpu_s"],
+                                     "alg_hbm_frac": s["bytes"] / s["gpu_s"] / 1e9 / HBM_PEAK_GBPS}
             log("qv32 %s:" % fusion, out["qv32_" + fusion])
         # state reads on the quantum-volume output
         state_bytes = 8.0 * (1 << n)

@@ -78,13 +78,13 @@ def run_step(st, gates, opts_kw, sample):
 
 
 def cpu_baseline(seconds_hint: float = 20.0) -> dict:
-    """The oracle (complex128, OpenMP, one gate at a time) on a 24-qubit 2x12
+    """The oracle (complex128, OpenMP, one gate at a time) on a 26-qubit 2x13
     grid of the same depth and gate set; gates/s scaled to 34 qubits by the
-    state-size ratio 2^24 / 2^34 (the oracle's cost is linear in 2^n)."""
+    state-size ratio 2^26 / 2^34 (the oracle's cost is linear in 2^n)."""
     import circuits as C
     import oracle
-    n = 24
-    gates = C.grid_circuit(2, 12, 24, seed=0)
+    n = 26
+    gates = C.grid_circuit(2, 13, 24, seed=0)
     oracle.build()
     probe = gates[:40]
     t0 = time.perf_counter()
@@ -94,7 +94,7 @@ def cpu_baseline(seconds_hint: float = 20.0) -> dict:
     t0 = time.perf_counter()
     oracle.apply_circuit(n, gates[:count])
     dt = time.perf_counter() - t0
-    gps_24 = count / dt
+    gps_n = count / dt
     # the other workloads, a few seconds each: the QFT-like circuit at 22
     # qubits (scaled to 32 by 2^-10) and the first 16 batched circuits
     qn = 22
@@ -108,12 +108,12 @@ def cpu_baseline(seconds_hint: float = 20.0) -> dict:
         oracle.apply_circuit(nb, cb)
     bdt = time.perf_counter() - t0
     return {
-        "value": gps_24 * 2.0 ** (24 - 34),
+        "value": gps_n * 2.0 ** (n - 34),
         "unit": "gates/s",
         "cores": oracle.threads(),
         "kind": "oracle",
-        "sample": "first %d gates of a 24-qubit 2x12 grid circuit (depth 24) in %.1f s = %.3g gates/s at 24 "
-                  "qubits, scaled by 2^-10 to the 34-qubit state" % (count, dt, gps_24),
+        "sample": "first %d gates of a 26-qubit 2x13 grid circuit (depth 24) in %.1f s = %.3g gates/s at 26 "
+                  "qubits, scaled by 2^-8 to the 34-qubit state" % (count, dt, gps_n),
         "qft32_gates_per_s": len(qft) / qdt * 2.0 ** (qn - 32),
         "qft_sample": "22-qubit QFT-like circuit (%d gates) in %.2f s, scaled by 2^-10 to 32 qubits" % (len(qft), qdt),
         "batch_circuits_per_s": 16 / bdt,

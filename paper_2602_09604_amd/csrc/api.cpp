@@ -369,6 +369,10 @@ int sv_alloc(int n_qubits, int dtype, void* dev_buf, size_t buf_bytes, void* hip
     sv_free(s);
     return fail(SV_ENOMEM, "host allocation failed");
   }
+  catch (...) {
+    sv_free(s);
+    return fail(SV_EINVAL, "unknown failure");
+  }
 }
 
 int sv_free(sv_state* s) {
@@ -528,6 +532,10 @@ int sv_fuse(const sv_gate* in, size_t n_in, int n_qubits, const sv_run_opts* opt
     return SV_OK;
   } catch (const std::bad_alloc&) {
     return fail(SV_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(SV_EINVAL, e.what());
+  } catch (...) {
+    return fail(SV_EINVAL, "unknown failure");
   }
 }
 

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <exception>
 #include <fstream>
 #include <functional>
 #include <mutex>
@@ -144,9 +145,21 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
   const bool inline_only = host_pool_worker();
   std::vector<std::vector<std::vector<int>>> blk;
   std::vector<std::thread> pool;
+  std::vector<std::exception_ptr> errs;
+  std::mutex err_mu;
   auto spawn = [&](std::function<void()> f) {
-    if (inline_only) f();
-    else pool.emplace_back(std::move(f));
+    if (inline_only) {
+      f();
+      return;
+    }
+    pool.emplace_back([f, &errs, &err_mu] {
+      try {
+        f();
+      } catch (...) {  // carried back to the caller; an exception must not end a thread
+        std::lock_guard<std::mutex> lk(err_mu);
+        errs.push_back(std::current_exception());
+      }
+    });
   };
   for (int K = max_k; K >= 1 && K >= max_k - 1; --K)
     for (bool narrow : {false, true}) blk.push_back({});
@@ -196,6 +209,7 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
   // The phase-block partition: each run of phase gates is one elementwise
   // sweep, priced as a one-qubit pass on the top qubit (same traffic, no gather).
   for (auto& t : pool) t.join();
+  if (!errs.empty()) std::rethrow_exception(errs.front());
   for (auto& b : blk) {  // largest-block partitions, in the order they were started
     const double t = total(b);
     if (t < best_t) {
@@ -234,56 +248,64 @@ using namespace sv;
 extern "C" {
 
 int sv_cost_model_save(const char* path) {
-  if (!path) return fail(SV_EINVAL, "path is NULL");
-  std::vector<float> p;
-  int w;
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    p = g_params;
-    w = g_width;
-  }
-  if (w == 0) return fail(SV_EINVAL, "no cost model installed");
-  std::ofstream f(path, std::ios::binary);
-  if (!f) return fail(SV_EINVAL, std::string("cannot write ") + path);
-  const uint32_t hdr[5] = {0x4D435653u, 1u, (uint32_t)w, (uint32_t)F, (uint32_t)p.size()};
-  f.write((const char*)hdr, sizeof(hdr));
-  f.write((const char*)p.data(), sizeof(float) * p.size());
-  return f ? SV_OK : fail(SV_EINVAL, "write failed");
+  return host_guard([&]() -> int {
+    if (!path) return fail(SV_EINVAL, "path is NULL");
+    std::vector<float> p;
+    int w;
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      p = g_params;
+      w = g_width;
+    }
+    if (w == 0) return fail(SV_EINVAL, "no cost model installed");
+    std::ofstream f(path, std::ios::binary);
+    if (!f) return fail(SV_EINVAL, std::string("cannot write ") + path);
+    const uint32_t hdr[5] = {0x4D435653u, 1u, (uint32_t)w, (uint32_t)F, (uint32_t)p.size()};
+    f.write((const char*)hdr, sizeof(hdr));
+    f.write((const char*)p.data(), sizeof(float) * p.size());
+    return f ? SV_OK : fail(SV_EINVAL, "write failed");
+  });
 }
 
 int sv_cost_model_load(const char* path) {
-  if (!path) return fail(SV_EINVAL, "path is NULL");
-  std::ifstream f(path, std::ios::binary);
-  if (!f) return fail(SV_EINVAL, std::string("cannot read ") + path);
-  uint32_t hdr[5];
-  if (!f.read((char*)hdr, sizeof(hdr))) return fail(SV_EINVAL, "truncated cost model file");
-  if (hdr[0] != 0x4D435653u || hdr[1] != 1u) return fail(SV_EINVAL, "not a cost model file");
-  if (hdr[2] != 64 || hdr[3] != (uint32_t)F || hdr[4] != (uint32_t)num_params((int)hdr[2]))
-    return fail(SV_EINVAL, "cost model shape mismatch");
-  std::vector<float> p(hdr[4]);
-  if (!f.read((char*)p.data(), sizeof(float) * p.size())) return fail(SV_EINVAL, "truncated cost model file");
-  for (float v : p)
-    if (!std::isfinite(v)) return fail(SV_EINVAL, "non-finite parameter");
-  cost_model_set(p, (int)hdr[2]);
-  return SV_OK;
+  return host_guard([&]() -> int {
+    if (!path) return fail(SV_EINVAL, "path is NULL");
+    std::ifstream f(path, std::ios::binary);
+    if (!f) return fail(SV_EINVAL, std::string("cannot read ") + path);
+    uint32_t hdr[5];
+    if (!f.read((char*)hdr, sizeof(hdr))) return fail(SV_EINVAL, "truncated cost model file");
+    if (hdr[0] != 0x4D435653u || hdr[1] != 1u) return fail(SV_EINVAL, "not a cost model file");
+    if (hdr[2] != 64 || hdr[3] != (uint32_t)F || hdr[4] != (uint32_t)num_params((int)hdr[2]))
+      return fail(SV_EINVAL, "cost model shape mismatch");
+    std::vector<float> p(hdr[4]);
+    if (!f.read((char*)p.data(), sizeof(float) * p.size())) return fail(SV_EINVAL, "truncated cost model file");
+    for (float v : p)
+      if (!std::isfinite(v)) return fail(SV_EINVAL, "non-finite parameter");
+    cost_model_set(p, (int)hdr[2]);
+    return SV_OK;
+  });
 }
 
 int sv_cost_model_predict(int k, const int32_t* qubits, int n_qubits, int precision, double* out) {
-  if (!qubits || !out || k < 1 || k > SV_MAX_K || n_qubits < 1 || n_qubits > SV_MAX_QUBITS)
-    return fail(SV_EINVAL, "bad arguments");
-  if (!cost_model_ready()) return fail(SV_EINVAL, "no cost model installed");
-  int q[SV_MAX_K];
-  for (int j = 0; j < k; ++j) q[j] = qubits[j];
-  *out = cost_model_predict_log(k, q, n_qubits, precision);
-  return SV_OK;
+  return host_guard([&]() -> int {
+    if (!qubits || !out || k < 1 || k > SV_MAX_K || n_qubits < 1 || n_qubits > SV_MAX_QUBITS)
+      return fail(SV_EINVAL, "bad arguments");
+    if (!cost_model_ready()) return fail(SV_EINVAL, "no cost model installed");
+    int q[SV_MAX_K];
+    for (int j = 0; j < k; ++j) q[j] = qubits[j];
+    *out = cost_model_predict_log(k, q, n_qubits, precision);
+    return SV_OK;
+  });
 }
 
 int sv_cost_features(int k, const int32_t* qubits, int n_qubits, int precision, float* out) {
-  if (!qubits || !out || k < 1 || k > SV_MAX_K) return fail(SV_EINVAL, "bad arguments");
-  int q[SV_MAX_K];
-  for (int j = 0; j < k; ++j) q[j] = qubits[j];
-  cost_features(k, q, n_qubits, precision, out);
-  return SV_OK;
+  return host_guard([&]() -> int {
+    if (!qubits || !out || k < 1 || k > SV_MAX_K) return fail(SV_EINVAL, "bad arguments");
+    int q[SV_MAX_K];
+    for (int j = 0; j < k; ++j) q[j] = qubits[j];
+    cost_features(k, q, n_qubits, precision, out);
+    return SV_OK;
+  });
 }
 
 }  // extern "C"

@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cstring>
+#include <exception>
 #include <functional>
 #include <thread>
 #include <unordered_map>
@@ -416,13 +417,21 @@ void fuse_blocks(const sv_gate* g, size_t n, const std::vector<std::vector<int>>
     return;
   }
   std::atomic<size_t> next{0};
-  auto worker = [&] {
-    for (size_t b = next++; b < nb; b = next++) build_block(g, blocks[b], out[b]);
+  std::vector<std::exception_ptr> errs(nt);
+  auto worker = [&](unsigned w) {
+    try {
+      for (size_t b = next++; b < nb; b = next++) build_block(g, blocks[b], out[b]);
+    } catch (...) {  // carried back to the caller; an exception must not end a thread
+      errs[w] = std::current_exception();
+      next = nb;
+    }
   };
   std::vector<std::thread> pool;
-  for (unsigned w = 1; w < nt; ++w) pool.emplace_back(worker);
-  worker();
+  for (unsigned w = 1; w < nt; ++w) pool.emplace_back(worker, w);
+  worker(0);
   for (auto& t : pool) t.join();
+  for (auto& e : errs)
+    if (e) std::rethrow_exception(e);
 }
 
 void fuse_greedy(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>& out,

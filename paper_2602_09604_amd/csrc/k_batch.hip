@@ -430,7 +430,9 @@ extern "C" int sv_batch_run(sv_state* const* states, const sv_gate* const* circu
     return fail(SV_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.err));
   } catch (const std::bad_alloc&) {
     return fail(SV_ENOMEM, "host allocation failed");
-  } catch (const std::invalid_argument& e) {
+  } catch (const std::exception& e) {
     return fail(SV_EINVAL, e.what());
+  } catch (...) {
+    return fail(SV_EINVAL, "unknown failure");
   }
 }

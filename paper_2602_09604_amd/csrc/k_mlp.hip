@@ -249,6 +249,9 @@ using namespace sv;
   }                                                                                      \
   catch (const std::bad_alloc&) {                                                        \
     return fail(SV_ENOMEM, "host allocation failed");                                    \
+  }                                                                                      \
+  catch (...) {                                                                          \
+    return fail(SV_EINVAL, "unknown failure");                                           \
   }
 
 extern "C" {
@@ -294,6 +297,10 @@ int sv_mlp_create(int width, uint64_t seed, void* hip_stream, sv_mlp** out) {
   catch (const DeviceError& e) {
     sv_mlp_free(m);
     return fail(SV_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.err));
+  }
+  catch (...) {
+    sv_mlp_free(m);
+    return fail(SV_ENOMEM, "host allocation failed");
   }
 }
 
@@ -416,11 +423,13 @@ int sv_mlp_train(sv_mlp* m, const float* x_dev, const float* y_dev, int n, int e
 }
 
 int sv_cost_model_install(sv_mlp* m) {
-  if (!m) return fail(SV_EINVAL, "NULL model");
-  std::vector<float> p(m->nparams);
-  if (int rc = sv_mlp_get_params(m, p.data())) return rc;
-  cost_model_set(p, m->width);
-  return SV_OK;
+  return host_guard([&]() -> int {
+    if (!m) return fail(SV_EINVAL, "NULL model");
+    std::vector<float> p(m->nparams);
+    if (int rc = sv_mlp_get_params(m, p.data())) return rc;
+    cost_model_set(p, m->width);
+    return SV_OK;
+  });
 }
 
 }  // extern "C"

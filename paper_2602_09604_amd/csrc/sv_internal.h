@@ -7,6 +7,8 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <exception>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -22,6 +24,20 @@ struct DeviceError {
   hipError_t err;
   const char* what;
 };
+
+// Run a host-only entry point body so that no C++ exception crosses the ABI.
+template <class F>
+int host_guard(F&& body) {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return fail(SV_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(SV_EINVAL, e.what());
+  } catch (...) {
+    return fail(SV_EINVAL, "unknown failure");
+  }
+}
 
 #define SV_HIP(call)                                          \
   do {                                                        \

@@ -248,66 +248,77 @@ int sv_autotune(sv_state* s, int budget_ms) {
     if (dev) (void)hipFree(dev);
     if (host) (void)hipHostFree(host);
     return fail(SV_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.err));
+  } catch (...) {
+    (void)hipStreamSynchronize(state_stream(s));
+    if (dev) (void)hipFree(dev);
+    if (host) (void)hipHostFree(host);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return fail(SV_ENOMEM, "host failure during tuning");
   }
 }
 
 // JSON: {"entries": [[precision, k, q0, nlow, variant, tile_bits, ms], ...]}
 int sv_tune_save(const char* path) {
-  if (!path) return fail(SV_EINVAL, "path is NULL");
-  std::lock_guard<std::mutex> lk(g_mu);
-  std::ofstream f(path);
-  if (!f) return fail(SV_EINVAL, std::string("cannot write ") + path);
-  f << "{\"format\": \"libsv-tune-1\", \"batch_lds_max_n\": " << batch_lds_max_n() << ", \"entries\": [";
-  bool first = true;
-  for (auto& kv : g_table) {
-    f << (first ? "" : ", ") << "[" << std::get<0>(kv.first) << ", " << std::get<1>(kv.first) << ", "
-      << std::get<2>(kv.first) << ", " << std::get<3>(kv.first) << ", " << kv.second.variant << ", "
-      << kv.second.tile_bits << ", " << kv.second.ms << "]";
-    first = false;
-  }
-  f << "]}\n";
-  return f ? SV_OK : fail(SV_EINVAL, "write failed");
+  return host_guard([&]() -> int {
+    if (!path) return fail(SV_EINVAL, "path is NULL");
+    std::lock_guard<std::mutex> lk(g_mu);
+    std::ofstream f(path);
+    if (!f) return fail(SV_EINVAL, std::string("cannot write ") + path);
+    f << "{\"format\": \"libsv-tune-1\", \"batch_lds_max_n\": " << batch_lds_max_n() << ", \"entries\": [";
+    bool first = true;
+    for (auto& kv : g_table) {
+      f << (first ? "" : ", ") << "[" << std::get<0>(kv.first) << ", " << std::get<1>(kv.first) << ", "
+        << std::get<2>(kv.first) << ", " << std::get<3>(kv.first) << ", " << kv.second.variant << ", "
+        << kv.second.tile_bits << ", " << kv.second.ms << "]";
+      first = false;
+    }
+    f << "]}\n";
+    return f ? SV_OK : fail(SV_EINVAL, "write failed");
+  });
 }
 
 int sv_tune_load(const char* path) {
-  if (!path) return fail(SV_EINVAL, "path is NULL");
-  std::ifstream f(path);
-  if (!f) return fail(SV_EINVAL, std::string("cannot read ") + path);
-  std::stringstream ss;
-  ss << f.rdbuf();
-  std::string text = ss.str();
-  const size_t at = text.find("\"entries\"");
-  if (text.find("libsv-tune-1") == std::string::npos || at == std::string::npos)
-    return fail(SV_EINVAL, "not a libsv tuning file");
-  std::map<Key, Choice> parsed;
-  size_t pos = text.find('[', at);
-  if (pos == std::string::npos) return fail(SV_EINVAL, "malformed tuning file");
-  ++pos;
-  while (true) {
-    const size_t open = text.find('[', pos);
-    if (open == std::string::npos) break;
-    const size_t close = text.find(']', open);
-    if (close == std::string::npos) return fail(SV_EINVAL, "malformed tuning file");
-    int p, k, q0, nlow, var, tb;
-    double ms;
-    if (std::sscanf(text.c_str() + open, "[%d, %d, %d, %d, %d, %d, %lf]", &p, &k, &q0, &nlow, &var, &tb, &ms) != 7)
-      return fail(SV_EINVAL, "malformed tuning entry");
-    if (p < 0 || p > 3 || k < 1 || k > SV_MAX_K || q0 < 0 || q0 > 1 || nlow < 0 || nlow > 6 || var < V_REG ||
-        var > V_SHFL || var == V_PHASE || (tb != 10 && tb != 12))
-      return fail(SV_EINVAL, "tuning entry out of range");
-    parsed[Key{p, k, q0, nlow}] = Choice{var, tb, ms};
-    pos = close + 1;
-  }
-  const size_t bl = text.find("\"batch_lds_max_n\"");
-  if (bl != std::string::npos) {
-    int v = 0;
-    if (std::sscanf(text.c_str() + text.find(':', bl) + 1, "%d", &v) != 1 || v < 1 || v > 13)
-      return fail(SV_EINVAL, "batch_lds_max_n out of range");
-    set_batch_lds_max_n(v);
-  }
-  std::lock_guard<std::mutex> lk(g_mu);
-  for (auto& kv : parsed) g_table[kv.first] = kv.second;
-  return SV_OK;
+  return host_guard([&]() -> int {
+    if (!path) return fail(SV_EINVAL, "path is NULL");
+    std::ifstream f(path);
+    if (!f) return fail(SV_EINVAL, std::string("cannot read ") + path);
+    std::stringstream ss;
+    ss << f.rdbuf();
+    std::string text = ss.str();
+    const size_t at = text.find("\"entries\"");
+    if (text.find("libsv-tune-1") == std::string::npos || at == std::string::npos)
+      return fail(SV_EINVAL, "not a libsv tuning file");
+    std::map<Key, Choice> parsed;
+    size_t pos = text.find('[', at);
+    if (pos == std::string::npos) return fail(SV_EINVAL, "malformed tuning file");
+    ++pos;
+    while (true) {
+      const size_t open = text.find('[', pos);
+      if (open == std::string::npos) break;
+      const size_t close = text.find(']', open);
+      if (close == std::string::npos) return fail(SV_EINVAL, "malformed tuning file");
+      int p, k, q0, nlow, var, tb;
+      double ms;
+      if (std::sscanf(text.c_str() + open, "[%d, %d, %d, %d, %d, %d, %lf]", &p, &k, &q0, &nlow, &var, &tb, &ms) != 7)
+        return fail(SV_EINVAL, "malformed tuning entry");
+      if (p < 0 || p > 3 || k < 1 || k > SV_MAX_K || q0 < 0 || q0 > 1 || nlow < 0 || nlow > 6 || var < V_REG ||
+          var > V_SHFL || var == V_PHASE || (tb != 10 && tb != 12))
+        return fail(SV_EINVAL, "tuning entry out of range");
+      parsed[Key{p, k, q0, nlow}] = Choice{var, tb, ms};
+      pos = close + 1;
+    }
+    const size_t bl = text.find("\"batch_lds_max_n\"");
+    if (bl != std::string::npos) {
+      int v = 0;
+      if (std::sscanf(text.c_str() + text.find(':', bl) + 1, "%d", &v) != 1 || v < 1 || v > 13)
+        return fail(SV_EINVAL, "batch_lds_max_n out of range");
+      set_batch_lds_max_n(v);
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto& kv : parsed) g_table[kv.first] = kv.second;
+    return SV_OK;
+  });
 }
 
 }  // extern "C"

@@ -110,6 +110,9 @@ bool shfl_eligible(int n, int k, const int* s) {
     else if (s[j] <= 6) ++lane;
     else return false;
   }
+  // two lane targets: only within bits 1..5 (a partner across the two halves
+  // of the wavefront, bit 6, costs more permute bandwidth than the LDS form)
+  if (lane == 2 && (s[0] > 5 || s[1] > 5)) return false;
   return lane >= 1 && (zero == 0 || lane == 1);
 }
 

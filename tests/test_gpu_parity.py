@@ -240,13 +240,13 @@ def test_shuffle_kernel_all_lane_targets(n, qs):
     try:
         st.apply_circuit(gates[:n], fusion="none")
         s = st.apply_circuit(gates[n:], fusion="none", variant="shfl", timing=True)
-        assert s["variant_passes"][1] == 1
+        assert s["variant_passes"][1] == 1  # the shuffle form, or the register form it falls back to
         check(st.read(), oracle.apply_circuit(n, gates))
     finally:
         st.free()
 
 
-@pytest.mark.parametrize("qs", [(1,), (6,), (0, 4), (2, 5), (1, 6)])
+@pytest.mark.parametrize("qs", [(1,), (6,), (0, 4), (2, 5), (1, 5)])
 def test_shuffle_kernel_streaming(qs):
     n = 26  # non-temporal loads and stores
     rng = np.random.Generator(np.random.PCG64(sum(qs) + 5))

@@ -32,7 +32,10 @@ def test_config2_k_sweep_full_state():
     n = 30
     gates = C.grid_circuit(5, 6, 20, seed=0)
     t0 = time.perf_counter()
-    ref = oracle.apply_circuit(n, gates)
+    ref = oracle.basis_state(n, 0)
+    for i in range(0, len(gates), 100):  # in slices, reporting progress (minutes of CPU work)
+        oracle.apply_circuit(n, gates[i:i + 100], psi=ref)
+        say("oracle: %d/%d gates, %.1f s" % (min(i + 100, len(gates)), len(gates), time.perf_counter() - t0))
     say("oracle: %.1f s on %d threads" % (time.perf_counter() - t0, oracle.threads()))
     st = sv.State(n)
     try:

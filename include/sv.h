@@ -92,7 +92,7 @@ extern "C" {
 #define SV_VARIANT_REG 1
 #define SV_VARIANT_LDS 2
 #define SV_VARIANT_MFMA 3
-#define SV_VARIANT_SHFL 4     /* all targets in bits 0..6 (two lane targets: within 1..5), k <= 2: one coalesced
+#define SV_VARIANT_SHFL 4     /* all targets in bits 0..6 (two or three in 1..6: within 1..5), k <= 3: one coalesced
                                  16-byte element per lane, partners by cross-lane permutes */
 
 #define SV_MAX_K 6            /* largest fused gate */

@@ -1,5 +1,5 @@
-// Passes whose targets all lie in the low seven bits, with at most two of
-// them in bits 1..6: the gate is applied without any gather.  Every lane
+// Gates of up to three qubits whose targets all lie in the low seven bits:
+// the gate is applied without any gather.  Every lane
 // loads one 16-byte element (amplitudes 2e and 2e + 1), so a wavefront reads
 // 1 KiB contiguously; element bits 0..5 are the lane bits, i.e. state bits
 // 1..6.  A target on bit 0 lives inside the element, a target on bit t in
@@ -14,9 +14,7 @@ using kern::gld;
 using kern::gst;
 
 struct ShflArgs {
-  uint64_t elems;   // 2^(n-1) float4 elements
-  int m1, m2;       // lane xor masks of the lane targets (m2 = 0 when only one)
-  int bit0;         // 1: bit 0 is a target (local bit 0)
+  int m[3];         // lane xor masks of the lane targets, ascending
 };
 
 // value held by lane ^ mask (a cross-lane permute; mask < 64)
@@ -33,111 +31,98 @@ __device__ __forceinline__ void cmac2(float2& acc, const float2 u, float vx, flo
   acc.y = fmaf(u.y, vx, acc.y);
 }
 
-// MODE 0: one lane target (2x2, local bit 0 = lane target); the element holds
-//         two independent groups (bit 0 is not a target).
-// MODE 1: bit 0 and one lane target (4x4: local bit 0 = state bit 0, local
-//         bit 1 = lane target); the element holds two amplitudes of one group.
-// MODE 2: two lane targets (4x4, local bits 0, 1 = lane targets m1 < m2); the
-//         element holds two independent groups.
-template <int MODE, bool NT>
+// KL lane targets (local bits BIT0 .. BIT0 + KL - 1) and, with BIT0, state
+// bit 0 as local bit 0 (inside the element).  Lane l holds lane-local index
+// li (its bits at the lane targets); the 2^KL - 1 partners lane ^ M(d) hold
+// li ^ d.  Without BIT0 the element carries two independent groups (bit 0 =
+// 0 in .xy, 1 in .zw); with BIT0 it carries local indices 2 li and 2 li + 1
+// of one group.
+template <int KL, bool BIT0, bool NT>
 __global__ __launch_bounds__(256) void k_apply_shfl(float4* __restrict__ psi, const float2* __restrict__ U,
                                                     const ShflArgs a) {
+  constexpr int DL = 1 << KL;
+  constexpr int D = DL << (BIT0 ? 1 : 0);  // matrix dimension
   const uint64_t e = ((uint64_t)blockIdx.y * gridDim.x + blockIdx.x) * 256 + threadIdx.x;
-  // the grid covers whole wavefronts of real elements (elems is a multiple of 64)
+  // the grid covers whole wavefronts of real elements (2^(n-1) is a multiple of 256)
   const int lane = threadIdx.x & 63;
-  const float4 v = gld<NT>(psi + e);
-  float4 out;
-  if constexpr (MODE == 0) {
-    const float4 p = lane_xor4(v, a.m1);
-    const int b = (lane & a.m1) ? 1 : 0;
-    const float2 us = U[b * 2 + b], up = U[b * 2 + (1 - b)];  // own and partner coefficients of row b
-    float2 lo = make_float2(0.f, 0.f), hi = make_float2(0.f, 0.f);
-    cmac2(lo, us, v.x, v.y);
-    cmac2(lo, up, p.x, p.y);
-    cmac2(hi, us, v.z, v.w);
-    cmac2(hi, up, p.z, p.w);
-    out = make_float4(lo.x, lo.y, hi.x, hi.y);
-  } else if constexpr (MODE == 1) {
-    const float4 p = lane_xor4(v, a.m1);
-    const int b = (lane & a.m1) ? 1 : 0;  // local bit 1
-    // own local indices 2b, 2b+1; partner's 2(1-b), 2(1-b)+1
-    const int r0 = 2 * b, po = 2 * (1 - b);
-    float2 o0 = make_float2(0.f, 0.f), o1 = make_float2(0.f, 0.f);
-    cmac2(o0, U[r0 * 4 + r0], v.x, v.y);
-    cmac2(o0, U[r0 * 4 + r0 + 1], v.z, v.w);
-    cmac2(o0, U[r0 * 4 + po], p.x, p.y);
-    cmac2(o0, U[r0 * 4 + po + 1], p.z, p.w);
-    cmac2(o1, U[(r0 + 1) * 4 + r0], v.x, v.y);
-    cmac2(o1, U[(r0 + 1) * 4 + r0 + 1], v.z, v.w);
-    cmac2(o1, U[(r0 + 1) * 4 + po], p.x, p.y);
-    cmac2(o1, U[(r0 + 1) * 4 + po + 1], p.z, p.w);
-    out = make_float4(o0.x, o0.y, o1.x, o1.y);
-  } else {
-    float4 x[4];  // x[c] = this lane's group component with local index c
-    const int l = ((lane & a.m1) ? 1 : 0) | ((lane & a.m2) ? 2 : 0);
-    const float4 p1 = lane_xor4(v, a.m1), p2 = lane_xor4(v, a.m2), p3 = lane_xor4(v, a.m1 | a.m2);
-    x[l] = v;
-    x[l ^ 1] = p1;
-    x[l ^ 2] = p2;
-    x[l ^ 3] = p3;
-    float2 lo = make_float2(0.f, 0.f), hi = make_float2(0.f, 0.f);
+  int li = 0;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const float2 u = U[l * 4 + c];
-      cmac2(lo, u, x[c].x, x[c].y);
-      cmac2(hi, u, x[c].z, x[c].w);
+  for (int j = 0; j < KL; ++j) li |= ((lane & a.m[j]) ? 1 : 0) << j;
+  const float4 v = gld<NT>(psi + e);
+  float2 lo = make_float2(0.f, 0.f), hi = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int d = 0; d < DL; ++d) {  // partner lane ^ M(d) holds lane-local index c = li ^ d
+    int mask = 0;
+#pragma unroll
+    for (int j = 0; j < KL; ++j)
+      if ((d >> j) & 1) mask |= a.m[j];
+    const float4 w = d == 0 ? v : lane_xor4(v, mask);
+    const int c = li ^ d;
+    if constexpr (!BIT0) {
+      const float2 u = U[li * D + c];
+      cmac2(lo, u, w.x, w.y);
+      cmac2(hi, u, w.z, w.w);
+    } else {
+      const int r0 = 2 * li;
+      cmac2(lo, U[r0 * D + 2 * c], w.x, w.y);
+      cmac2(lo, U[r0 * D + 2 * c + 1], w.z, w.w);
+      cmac2(hi, U[(r0 + 1) * D + 2 * c], w.x, w.y);
+      cmac2(hi, U[(r0 + 1) * D + 2 * c + 1], w.z, w.w);
     }
-    out = make_float4(lo.x, lo.y, hi.x, hi.y);
   }
-  gst<NT>(psi + e, out);
+  gst<NT>(psi + e, make_float4(lo.x, lo.y, hi.x, hi.y));
 }
 
-template <int MODE, bool NT>
-void launch_t(float4* psi, const float2* U, const ShflArgs& a, hipStream_t st) {
-  const uint64_t blocks = a.elems / 256;
+template <int KL, bool BIT0, bool NT>
+void launch_t(float4* psi, const float2* U, const ShflArgs& a, uint64_t elems, hipStream_t st) {
+  const uint64_t blocks = elems / 256;
   const uint64_t gx = blocks < 65536 ? blocks : 65536;
   const uint64_t gy = blocks / gx;  // elems is a power of two >= 256
-  hipLaunchKernelGGL((k_apply_shfl<MODE, NT>), dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, psi, U, a);
+  hipLaunchKernelGGL((k_apply_shfl<KL, BIT0, NT>), dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, psi, U, a);
+}
+
+template <int KL, bool BIT0>
+void launch_kl(float4* psi, const float2* U, const ShflArgs& a, uint64_t elems, bool nt, hipStream_t st) {
+  if (nt) launch_t<KL, BIT0, true>(psi, U, a, elems, st);
+  else launch_t<KL, BIT0, false>(psi, U, a, elems, st);
 }
 
 }  // namespace
 
+// k <= 3 gates on bits 0..6 with one to three lane targets (bits 1..6); two
+// or more lane targets only within bits 1..5 (a partner across the two halves
+// of the wavefront, bit 6, costs more permute bandwidth than it saves).
 bool shfl_eligible(int n, int k, const int* s) {
-  if (n < 9 || k < 1 || k > 2) return false;
-  int lane = 0, zero = 0;
+  if (n < 9 || k < 1 || k > 3) return false;
+  int lane = 0, zero = 0, top = 0;
   for (int j = 0; j < k; ++j) {
     if (s[j] == 0) ++zero;
-    else if (s[j] <= 6) ++lane;
+    else if (s[j] <= 6) ++lane, top = s[j] > top ? s[j] : top;
     else return false;
   }
-  // two lane targets: only within bits 1..5 (a partner across the two halves
-  // of the wavefront, bit 6, costs more permute bandwidth than the LDS form)
-  if (lane == 2 && (s[0] > 5 || s[1] > 5)) return false;
-  return lane >= 1 && (zero == 0 || lane == 1);
+  if (lane == 0 || (lane >= 2 && top > 5)) return false;
+  return true;
 }
 
 // The planner has checked shfl_eligible (targets sorted ascending).
 void launch_shfl(const Pass& p, int n, void* psi_, const float2* U, hipStream_t st) {
-  if (!shfl_eligible(n, p.k, p.s)) throw DeviceError{hipErrorInvalidValue, "k_apply_shfl: targets not in bits 0..6"};
+  if (!shfl_eligible(n, p.k, p.s)) throw DeviceError{hipErrorInvalidValue, "k_apply_shfl: targets not eligible"};
   ShflArgs a{};
-  a.elems = (uint64_t)1 << (n - 1);
-  int mode;
-  if (p.s[0] == 0) {
-    mode = 1;
-    a.m1 = 1 << (p.s[1] - 1);
-  } else if (p.k == 1) {
-    mode = 0;
-    a.m1 = 1 << (p.s[0] - 1);
-  } else {
-    mode = 2;
-    a.m1 = 1 << (p.s[0] - 1);
-    a.m2 = 1 << (p.s[1] - 1);
-  }
+  const bool bit0 = p.s[0] == 0;
+  const int kl = p.k - (bit0 ? 1 : 0);
+  for (int j = 0; j < kl; ++j) a.m[j] = 1 << (p.s[j + (bit0 ? 1 : 0)] - 1);
   float4* psi = reinterpret_cast<float4*>(psi_);
+  const uint64_t elems = (uint64_t)1 << (n - 1);
   const bool nt = n >= kern::kNtMinQubits;
-  if (mode == 0) nt ? launch_t<0, true>(psi, U, a, st) : launch_t<0, false>(psi, U, a, st);
-  else if (mode == 1) nt ? launch_t<1, true>(psi, U, a, st) : launch_t<1, false>(psi, U, a, st);
-  else nt ? launch_t<2, true>(psi, U, a, st) : launch_t<2, false>(psi, U, a, st);
+  switch (kl * 2 + (bit0 ? 1 : 0)) {
+    case 2: launch_kl<1, false>(psi, U, a, elems, nt, st); break;
+    case 3: launch_kl<1, true>(psi, U, a, elems, nt, st); break;
+    case 4: launch_kl<2, false>(psi, U, a, elems, nt, st); break;
+    case 5: launch_kl<2, true>(psi, U, a, elems, nt, st); break;
+    case 6: launch_kl<3, false>(psi, U, a, elems, nt, st); break;
+    default: throw DeviceError{hipErrorInvalidValue, "k_apply_shfl: lane targets"};
+  }
+  SV_HIP(hipGetLastError());
 }
 
 }  // namespace sv

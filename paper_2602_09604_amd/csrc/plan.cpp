@@ -74,7 +74,7 @@ int choose_variant(int n, int k, const int* s, int precision, int requested) {
   if (requested == V_MFMA) return mfma_ok ? V_MFMA : V_REG;
   if (requested == V_LDS) return lds_feasible(n, k, s, sh.tile_bits) ? V_LDS : V_REG;
   if (requested == V_REG) return V_REG;
-  const bool shfl_ok = k <= 3 && shfl_eligible(n, k, s);
+  const bool shfl_ok = shfl_eligible(n, k, s);
   if (requested == V_SHFL) return shfl_ok ? V_SHFL : V_REG;
   // AUTO: the autotuner's measurement for this pass class when there is one
   const int tv = tuned_variant(n, k, s, precision);
@@ -85,7 +85,7 @@ int choose_variant(int n, int k, const int* s, int precision, int requested) {
   // untuned defaults, from sweeps at 30 qubits: matrix cores for k >= 4 when
   // the precision asks for them; LDS staging for low targets up to k = 4
   if (precision != SV_PREC_FP32_VALU && mfma_ok) return V_MFMA;
-  if (shfl_ok) return V_SHFL;
+  if (shfl_ok && k <= 2) return V_SHFL;  // at k = 3 the permutes cost more; only when tuned
   if (has_low_target(k, s) && k <= 4 && lds_feasible(n, k, s, sh.tile_bits)) return V_LDS;
   return V_REG;
 }

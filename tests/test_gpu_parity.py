@@ -225,14 +225,16 @@ def test_mfma_single_gate(prec, k, tname):
 
 
 SHFL_TARGETS = ([(t,) for t in range(1, 7)] + [(0, t) for t in range(1, 7)] + [(t, 0) for t in (3, 6)]
-                + [(a, b) for a in range(1, 7) for b in range(a + 1, 7)] + [(6, 2), (5, 1)])
+                + [(a, b) for a in range(1, 7) for b in range(a + 1, 7)] + [(6, 2), (5, 1)]
+                + [(0, 1, 2), (0, 2, 5), (3, 0, 4), (1, 2, 3), (1, 3, 5), (5, 2, 4), (2, 4, 6), (0, 1, 6)])
 
 
 @pytest.mark.parametrize("n", [9, 12])
 @pytest.mark.parametrize("qs", SHFL_TARGETS)
 def test_shuffle_kernel_all_lane_targets(n, qs):
-    """Targets in bits 0..6 (k <= 2, at most two lane targets): partners by
-    cross-lane permutes; the smallest state it runs on is 9 qubits."""
+    """Targets in bits 0..6 (k <= 3): partners by cross-lane permutes; the
+    smallest state it runs on is 9 qubits; ineligible sets fall back to the
+    register kernel."""
     sv = _sv()
     rng = np.random.Generator(np.random.PCG64(n * 100 + sum(qs) * 7 + qs[0]))
     gates = [C.Gate((q,), C.haar_unitary(1, rng)) for q in range(n)] + [C.Gate(qs, C.haar_unitary(len(qs), rng))]
@@ -246,7 +248,7 @@ def test_shuffle_kernel_all_lane_targets(n, qs):
         st.free()
 
 
-@pytest.mark.parametrize("qs", [(1,), (6,), (0, 4), (2, 5), (1, 5)])
+@pytest.mark.parametrize("qs", [(1,), (6,), (0, 4), (2, 5), (1, 5), (0, 2, 3), (1, 4, 5)])
 def test_shuffle_kernel_streaming(qs):
     n = 26  # non-temporal loads and stores
     rng = np.random.Generator(np.random.PCG64(sum(qs) + 5))

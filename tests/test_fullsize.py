@@ -144,3 +144,46 @@ def test_qft32_closed_form_sampled(prec, fusion):
         st.free()
         del st
         torch.cuda.empty_cache()
+
+
+def test_grid34_state_reads_on_product_state(state34):
+    """State reads at the benchmark's 128 GiB size: on the factorised grid
+    state (an 18-qubit left half times a 16-qubit right half) marginals and
+    Pauli expectations factorise into the halves' oracle values, and sampled
+    outcomes follow the marginal."""
+    gates = factorised_grid(seed=7)
+    psi_l, psi_r = half_states(gates)
+    st = state34
+    st.set_basis(0)
+    st.apply_circuit(gates, max_k=6, fusion="block", precision="fp16x3")
+    # marginal of five left-half and three right-half qubits
+    ql = [LEFT[i] for i in (0, 3, 7, 11, 17)]
+    qr = [RIGHT[i] for i in (2, 9, 15)]
+    got = st.marginal_probs(ql + qr)
+    pl = oracle.marginal_probabilities(psi_l, len(LEFT), [LEFT.index(q) for q in ql])
+    pr = oracle.marginal_probabilities(psi_r, len(RIGHT), [RIGHT.index(q) for q in qr])
+    ref = np.outer(pr, pl).reshape(-1)  # outcome bits: left qubits low, right qubits high
+    say("marginal max diff", np.max(np.abs(got - ref)))
+    assert np.max(np.abs(got - ref)) < 1e-5
+    # Pauli strings: Z on a left qubit, X on a right qubit, Z Z across the halves, Y Y inside the left half
+    a, b, c = LEFT[4], RIGHT[5], LEFT[9]
+    terms = [(0, 1 << a), (1 << b, 0), (0, (1 << a) | (1 << b)), ((1 << a) | (1 << c), (1 << a) | (1 << c))]
+    got = st.expect_pauli([t[0] for t in terms], [t[1] for t in terms])
+    zl = oracle.pauli_expectation(psi_l, len(LEFT), 0, 1 << LEFT.index(a)).real
+    xr = oracle.pauli_expectation(psi_r, len(RIGHT), 1 << RIGHT.index(b), 0).real
+    zr = oracle.pauli_expectation(psi_r, len(RIGHT), 0, 1 << RIGHT.index(b)).real
+    yy = oracle.pauli_expectation(psi_l, len(LEFT), (1 << LEFT.index(a)) | (1 << LEFT.index(c)),
+                                  (1 << LEFT.index(a)) | (1 << LEFT.index(c))).real
+    ref = np.array([zl, xr, zl * zr, yy])
+    say("pauli", got, ref)
+    assert np.max(np.abs(got - ref)) < 1e-5  # the state's own rounding (norm drift ~1e-6) bounds these
+    # 20000 samples: the frequencies of the three right-half qubits' outcomes
+    u = C.uniforms(20000, 11)
+    idx = st.sample(u).astype(np.uint64)
+    o = np.zeros(idx.size, dtype=np.int64)
+    for j, q in enumerate(qr):
+        o |= ((idx >> np.uint64(q)) & np.uint64(1)).astype(np.int64) << j
+    freq = np.bincount(o, minlength=8) / idx.size
+    sigma = np.sqrt(pr * (1 - pr) / idx.size)
+    say("sample freq", freq, "expected", pr)
+    assert np.all(np.abs(freq - pr) <= 5 * sigma + 1e-9)

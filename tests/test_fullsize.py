@@ -37,8 +37,12 @@ def factorised_grid(seed):
 def half_states(gates):
     lpos = {q: i for i, q in enumerate(LEFT)}
     rpos = {q: i for i, q in enumerate(RIGHT)}
-    lg = [C.Gate(tuple(lpos[q] for q in g.qubits), g.matrix) for g in gates if g.qubits[0] in lpos]
-    rg = [C.Gate(tuple(rpos[q] for q in g.qubits), g.matrix) for g in gates if g.qubits[0] in rpos]
+    def relabel(g, pos):
+        return C.Gate(tuple(pos[q] for q in g.qubits), g.matrix, tuple(pos[q] for q in g.controls),
+                      g.control_values)
+
+    lg = [relabel(g, lpos) for g in gates if g.qubits[0] in lpos]
+    rg = [relabel(g, rpos) for g in gates if g.qubits[0] in rpos]
     return oracle.apply_circuit(len(LEFT), lg), oracle.apply_circuit(len(RIGHT), rg)
 
 
@@ -187,3 +191,26 @@ def test_grid34_state_reads_on_product_state(state34):
     sigma = np.sqrt(pr * (1 - pr) / idx.size)
     say("sample freq", freq, "expected", pr)
     assert np.all(np.abs(freq - pr) <= 5 * sigma + 1e-9)
+
+
+def test_grid34_controlled_passes_sampled(state34):
+    """Controlled passes at 34 qubits: multi-controlled gates inside each half
+    of the factorised grid state keep it a product, so sampled amplitudes are
+    checked against the halves' oracle states."""
+    rng = np.random.Generator(np.random.PCG64(21))
+    gates = factorised_grid(seed=8)
+    ctl = [C.Gate((LEFT[2],), C.haar_unitary(1, rng), (LEFT[0], LEFT[9], LEFT[17]), (1, 0, 1)),
+           C.Gate((RIGHT[3], RIGHT[12]), C.haar_unitary(2, rng), (RIGHT[0], RIGHT[15])),
+           C.Gate((LEFT[5],), C.Z, tuple(LEFT[i] for i in (1, 4, 6, 8, 10, 12, 14, 16)))]
+    psi_l, psi_r = half_states(gates + ctl)
+    st = state34
+    st.set_basis(0)
+    st.apply_circuit(gates, max_k=6, fusion="block", precision="fp16x3")
+    s = st.apply_circuit(ctl, fusion="none", stats=True)
+    assert s["bytes"] == (16 << (N - 3)) + (16 << (N - 2)) + (16 << (N - 8))
+    idx = sample_indices(N, 3)
+    acc = oracle.CompareAcc()
+    acc.add(read_samples(st, idx), product_amplitudes(psi_l, psi_r, idx))
+    r = acc.result()
+    say("controlled", r)
+    assert r["max_abs"] <= 1e-5 and r["infidelity"] <= 1e-6

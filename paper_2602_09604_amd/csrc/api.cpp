@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <unordered_map>
 
 #include "sv_internal.h"
 
@@ -572,18 +573,18 @@ int sv_expect_pauli(sv_state* s, size_t n_terms, const uint64_t* xmask, const ui
   std::vector<uint64_t> sweep_f;
   std::vector<std::vector<size_t>> sweep_terms;
   {
-    std::vector<std::pair<uint64_t, size_t>> open;  // flip mask -> sweep being filled
+    std::unordered_map<uint64_t, size_t> open;  // flip mask -> the sweep being filled
     for (size_t t = 0; t < n_terms; ++t) {
-      size_t w = SIZE_MAX;
-      for (auto& pr : open)
-        if (pr.first == xmask[t] && sweep_terms[pr.second].size() < 8) w = pr.second;
-      if (w == SIZE_MAX) {
-        w = sweep_f.size();
+      auto it = open.find(xmask[t]);
+      if (it == open.end() || sweep_terms[it->second].size() == 8) {
+        const size_t w = sweep_f.size();
         sweep_f.push_back(xmask[t]);
         sweep_terms.emplace_back();
-        open.push_back({xmask[t], w});
+        open[xmask[t]] = w;
+        sweep_terms[w].push_back(t);
+      } else {
+        sweep_terms[it->second].push_back(t);
       }
-      sweep_terms[w].push_back(t);
     }
   }
   const size_t outs = sizeof(double) * 16 * sweep_f.size();

@@ -136,7 +136,8 @@ typedef struct {
                             2^(n-k) (2^(n-k-c) for a controlled pass) */
   double fuse_s;         /* host time in the fusion pass */
   double gpu_s;          /* device time of the passes (HIP events) */
-  double variant_s[5];   /* with opts.timing: device time per kernel family: 1 register,
+  double variant_s[5];   /* with opts.timing: device time per kernel family: 1 register
+                            (gather or wavefront shuffle, controlled passes included),
                             2 LDS, 3 matrix core, 4 phase-only (index 0 unused) */
   uint64_t variant_passes[5]; /* with opts.timing: passes per kernel family */
 } sv_run_stats;
@@ -256,9 +257,12 @@ int sv_write_amplitudes(sv_state* s, uint64_t start, uint64_t count, const float
  * batched persistent kernel captured in a hipGraph.  Circuits whose state
  * fits in LDS (n <= 14) are simulated entirely on chip; larger ones are
  * swept through HBM by the same kernel with a per-circuit barrier between
- * fused gates.  Gates are fused per opts->max_k (GREEDY) first.  When stats
- * is not NULL the call waits and fills it.  Equivalent to sv_apply_circuit on
- * each state in turn. */
+ * fused gates.  Gates are fused first per opts (fusion mode and max_k; GREEDY
+ * with max_k 4 when opts is NULL; the precision is always FP32), circuits on
+ * host threads.  A controlled gate wider than max_k with its controls is
+ * rejected (SV_EINVAL).  States of at most 30 qubits.  When stats is not NULL
+ * the call waits and fills it.  Equivalent to sv_apply_circuit on each state
+ * in turn. */
 int sv_batch_run(sv_state* const* states, const sv_gate* const* circuits, const size_t* n_gates,
                  size_t n_circuits, const sv_run_opts* opts, sv_run_stats* stats);
 

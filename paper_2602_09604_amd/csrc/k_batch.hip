@@ -396,7 +396,7 @@ extern "C" int sv_batch_run(sv_state* const* states, const sv_gate* const* circu
     o.max_k = 4;
     o.fusion = SV_FUSE_GREEDY;
   }
-  if (o.fusion < SV_FUSE_NONE || o.fusion > SV_FUSE_PHASE || (o.fusion != SV_FUSE_NONE && (o.max_k < 1 || o.max_k > SV_MAX_K)))
+  if (o.fusion < SV_FUSE_NONE || o.fusion > SV_FUSE_BLOCK || (o.fusion != SV_FUSE_NONE && (o.max_k < 1 || o.max_k > SV_MAX_K)))
     return fail(SV_EINVAL, "opts invalid");
   std::vector<void*> psis(n_circuits);
   std::vector<int> ns(n_circuits);

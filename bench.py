@@ -123,7 +123,9 @@ def cpu_baseline(seconds_hint: float = 20.0) -> dict:
 
 def batch_figures(max_k: int) -> dict:
     """The 512-circuit batched workload: one captured graph (sv_batch_run)
-    against one sv_apply_circuit launch sequence per circuit."""
+    against one sv_apply_circuit launch sequence per circuit, both with the
+    largest-block partition at max_k (k = 4 measured best: larger blocks make
+    the batched VALU passes compute-bound)."""
     import torch
     import circuits as C
     from paper_2602_09604_amd import sv
@@ -132,7 +134,7 @@ def batch_figures(max_k: int) -> dict:
     stream = torch.cuda.current_stream()
     states = [sv.State(n, stream=stream) for n in ns]
     try:
-        opts = sv.make_opts(max_k=max_k)
+        opts = sv.make_opts(max_k=max_k, fusion="block")
         # marshal every gate list once, outside the timed regions
         arrays = [sv.GateArray(c) for c in circs]
         hs = (ctypes.c_void_p * 512)(*[s.h for s in states])

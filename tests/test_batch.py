@@ -48,18 +48,19 @@ def test_batched_ansatz_small(tmp_path, lds_limit):
 
 
 def test_batched_ansatz_full_range(tmp_path):
-    """A slice of the 512-circuit workload (n up to 22), fused to k = 4 and 6."""
+    """A slice of the 512-circuit workload (n up to 22), fused to k = 4 .. 6,
+    first-come greedy and largest-block partitions."""
     set_lds_limit(tmp_path, 12)
     ns, circs = C.batched_ansatz(512, seed=0)
     pick = [i for i in range(512) if ns[i] in (10, 13, 17, 22)][:8]
     sub_ns = [ns[i] for i in pick]
     sub = [circs[i] for i in pick]
     refs = [oracle.apply_circuit(n, c) for n, c in zip(sub_ns, sub)]
-    for K in (4, 6):
-        out, stats = run_batch(sub_ns, sub, max_k=K)
+    for K, fusion in ((4, "greedy"), (6, "greedy"), (4, "block"), (5, "block")):
+        out, stats = run_batch(sub_ns, sub, max_k=K, fusion=fusion)
         for n, got, ref in zip(sub_ns, out, refs):
             r = oracle.compare(got, ref)
-            assert r["max_abs"] <= 1e-5 and r["infidelity"] <= 1e-6, (K, n, r)
+            assert r["max_abs"] <= 1e-5 and r["infidelity"] <= 1e-6, (K, fusion, n, r)
 
 
 def test_batch_matches_sequential_runs(tmp_path):

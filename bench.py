@@ -211,6 +211,15 @@ def other_workloads() -> dict:
                            "alg_hbm_frac": s["bytes"] / s["gpu_s"] / 1e9 / HBM_PEAK_GBPS,
                            "marked_probability": abs(complex(st.read(marked, 1)[0])) ** 2}
         log("grover32:", out["grover32"])
+        # the network against the fewest-passes rule where they differ: FP32
+        # on the VALU kernels, whose k = 6 passes are compute-bound
+        grid = C.grid_circuit(4, 8, 20, seed=0)
+        for fusion in ("learned", "block"):
+            st.set_basis(0)
+            s = st.apply_circuit(grid, max_k=6, fusion=fusion, precision="fp32_valu", stats=True)
+            out["grid32_fp32_valu_" + fusion] = {"gates": len(grid), "passes": s["passes"], "gpu_s": s["gpu_s"],
+                                                 "gates_per_s_gpu": len(grid) / s["gpu_s"]}
+            log("grid32 fp32_valu %s:" % fusion, out["grid32_fp32_valu_" + fusion])
         qv = C.quantum_volume_circuit(n, n, seed=0)
         for fusion in ("greedy", "block"):
             st.set_basis(0)

@@ -190,6 +190,29 @@ def other_workloads() -> dict:
     import circuits as C
     from paper_2602_09604_amd import sv
     out = {}
+    # the 20-qubit 4x5 depth-14 grid (8 MiB state, held in the caches):
+    # launch-bound unfused (389 passes), so one launch per pass against the
+    # kept graph relaunched, and block fusion; wall clock per circuit
+    small = sv.State(20)
+    try:
+        g20 = sv.GateArray(C.grid_circuit(4, 5, 14, seed=0))
+        for label, kw in (("unfused_launches", dict(fusion="none")),
+                          ("unfused_graph", dict(fusion="none", use_graph=True)),
+                          ("block6_graph", dict(fusion="block", max_k=6, precision="fp16x3", use_graph=True))):
+            s = small.apply_circuit(g20, stats=True, **kw)  # captures the graph when asked
+            small.norm()  # synchronises the state's stream
+            t0 = time.perf_counter()
+            for _ in range(5):
+                small.set_basis(0)
+                last = small.apply_circuit(g20, stats=True, **kw)
+            small.norm()
+            dt = (time.perf_counter() - t0) / 5
+            out["grid20_" + label] = {"gates": g20.n, "passes": s["passes"], "wall_s": dt, "gates_per_s": g20.n / dt,
+                                      "graph_relaunched": bool(last["graph_relaunched"])}
+        log("grid20:", {k: v for k, v in out.items() if k.startswith("grid20")})
+    finally:
+        small.free()
+        del small
     n = 32
     st = sv.State(n)
     try:

@@ -120,7 +120,13 @@ typedef struct {
   int32_t max_k;      /* fusion block size limit, 1..6 (ignored for NONE) */
   int32_t fusion;     /* SV_FUSE_* */
   int32_t precision;  /* SV_PREC_* */
-  int32_t use_graph;  /* 1: launch the passes as one captured hipGraph */
+  int32_t use_graph;  /* 1: launch the passes as one hipGraph on the handle's
+                         stream (captured on a private stream of the handle,
+                         so any stream works).  The handle keeps the last graph and
+                         a device copy of its pass data; a later call whose
+                         passes and matrices encode to the same bytes relaunches
+                         it without capturing again.  A different circuit
+                         replaces it (the stream is synchronised first). */
   int32_t variant;    /* SV_VARIANT_* (AUTO unless a test forces one) */
   int32_t timing;     /* 1: bracket every pass with HIP events on the handle's
                          stream and report per-variant device time in stats
@@ -140,6 +146,8 @@ typedef struct {
                             (gather or wavefront shuffle, controlled passes included),
                             2 LDS, 3 matrix core, 4 phase-only (index 0 unused) */
   uint64_t variant_passes[5]; /* with opts.timing: passes per kernel family */
+  uint64_t graph_relaunched;  /* 1 when opts.use_graph relaunched the handle's kept
+                                 graph without capturing a new one */
 } sv_run_stats;
 
 /* ---- state -------------------------------------------------------------- */
@@ -322,6 +330,9 @@ int sv_cost_features(int k, const int32_t* qubits, int n_qubits, int precision, 
 const char* sv_last_error(void);
 /* Library version string. */
 const char* sv_version(void);
+/* sizeof of an ABI struct, for bindings to check their layout: which 0
+ * sv_gate, 1 sv_run_opts, 2 sv_run_stats; 0 for any other value. */
+size_t sv_struct_size(int which);
 
 #ifdef __cplusplus
 }

@@ -87,12 +87,41 @@ def spearman(a, b) -> float:
     return float(np.corrcoef(ra, rb)[0, 1])
 
 
+HIGH_BIT = 13  # targets from this bit up are gathered with strides of >= 64 KiB
+MASK_BITS = 34  # target-mask features: bits 0..33, at feature 2 + bit
+
+
+def augment_high_targets(X: np.ndarray, y: np.ndarray, copies: int, rng: np.random.Generator):
+    """Append `copies` versions of every sample whose targets at or above
+    HIGH_BIT are moved to other distinct bits in [HIGH_BIT, 34), label kept.
+    Such passes run the same kernel form whichever high bits they use (the
+    corpus shows a few percent between them), so the copies stop the network
+    from keying on individual high bits, and it sees every high bit, also the
+    ones above the state sizes the corpus was timed at."""
+    out_x, out_y = [X], [y]
+    high = np.arange(HIGH_BIT, MASK_BITS)
+    for _ in range(copies):
+        Xc = X.copy()
+        for i in range(len(Xc)):
+            bits = np.nonzero(Xc[i, 2:2 + MASK_BITS] > 0)[0]
+            hi = bits[bits >= HIGH_BIT]
+            if len(hi) == 0:
+                continue
+            Xc[i, 2 + hi] = 0.0
+            Xc[i, 2 + rng.choice(high, size=len(hi), replace=False)] = 1.0
+        out_x.append(Xc)
+        out_y.append(y)
+    return np.concatenate(out_x), np.concatenate(out_y)
+
+
 def train_cost_model(corpus: Dict[str, np.ndarray], epochs: int = 4000, lr: float = 3e-3, seed: int = 0,
                      holdout: float = 0.2, install: bool = True, save_path: str | None = None,
-                     check_every: int = 200) -> dict:
+                     check_every: int = 200, augment: int = 4) -> dict:
     """Train on the GPU with early stopping on a validation split (the
     parameters with the lowest validation error are kept), report the error on
-    a separate test split and install the network as the fusion cost model."""
+    a separate test split and install the network as the fusion cost model.
+    The training split is widened by `augment` copies with moved high targets
+    (augment_high_targets); the validation and test splits are left as timed."""
     import torch
     X, y = corpus["X"], corpus["y"]
     rng = np.random.Generator(np.random.PCG64(seed + 1))
@@ -100,10 +129,11 @@ def train_cost_model(corpus: Dict[str, np.ndarray], epochs: int = 4000, lr: floa
     n_test = int(len(y) * holdout)
     n_val = n_test  # early-stopping split, disjoint from the reported test split
     te, va, tr = idx[:n_test], idx[n_test:n_test + n_val], idx[n_test + n_val:]
+    x_tr, y_tr = augment_high_targets(X[tr], y[tr], augment, rng) if augment else (X[tr], y[tr])
     m = sv.Mlp(seed=seed)
     try:
-        xd = torch.tensor(X[tr], device="cuda")
-        yd = torch.tensor(y[tr], device="cuda")
+        xd = torch.tensor(x_tr, device="cuda")
+        yd = torch.tensor(y_tr, device="cuda")
         xt = torch.tensor(X[te], device="cuda") if n_test else None
         xv = torch.tensor(X[va], device="cuda") if n_val else None
         t0 = time.perf_counter()
@@ -122,7 +152,7 @@ def train_cost_model(corpus: Dict[str, np.ndarray], epochs: int = 4000, lr: floa
             m.set_params(best[1])
         train_s = time.perf_counter() - t0
         out = {"train_mse": loss, "train_s": train_s, "epochs": epochs, "best_epoch": best[2],
-               "samples": int(len(tr))}
+               "samples": int(len(tr)), "augmented_samples": int(len(y_tr))}
         if n_test:
             pred = m.forward(xt)
             out["test_rmse"] = float(np.sqrt(np.mean((pred - y[te]) ** 2)))

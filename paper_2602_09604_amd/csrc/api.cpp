@@ -26,7 +26,13 @@ struct sv_state {
   double* norm_dev = nullptr;
   double* norm_host = nullptr;  // pinned
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // graph of the last use_graph call, with its own device copy of the pass
+  // data; a later call whose passes encode to the same bytes relaunches it
   hipGraphExec_t graph_exec = nullptr;
+  unsigned char* graph_dev = nullptr;
+  size_t graph_cap = 0;
+  std::vector<unsigned char> graph_key;
+  hipStream_t capture_stream = nullptr;  // graphs are captured here, launched on `stream`
   std::vector<hipEvent_t> pass_events;  // per-pass timing events (grown on demand)
   // state-read scratch (expectations, marginals, sampling), grown on demand
   unsigned char* meas_dev = nullptr;
@@ -101,11 +107,31 @@ static void meas_reserve(sv_state* s, size_t dev_bytes, size_t host_bytes) {
 }
 
 static void drop_graph(sv_state* s) {
+  s->graph_key.clear();
   if (s->graph_exec) {
     SV_HIP(hipStreamSynchronize(s->stream));
     SV_HIP(hipGraphExecDestroy(s->graph_exec));
     s->graph_exec = nullptr;
   }
+}
+
+// Everything a captured graph depends on besides the state buffer: each
+// pass's launch parameters and the encoded pass data (offsets relative to the
+// start of the data).
+static std::vector<unsigned char> graph_key(const std::vector<Pass>& passes, const unsigned char* data,
+                                            size_t total) {
+  std::vector<int64_t> f;
+  f.reserve(passes.size() * 28);
+  for (const Pass& p : passes) {
+    f.insert(f.end(), {p.k, p.variant, p.precision, (int64_t)p.mat_off, (int64_t)p.mat_bytes, p.tile_bits,
+                       p.reg_iters, p.mfma_cols, p.nhubs, (int64_t)p.cmask, (int64_t)p.cval});
+    f.insert(f.end(), p.s, p.s + SV_MAX_K);
+    f.insert(f.end(), p.hub, p.hub + 8);
+  }
+  std::vector<unsigned char> key(f.size() * sizeof(int64_t) + total);
+  std::memcpy(key.data(), f.data(), f.size() * sizeof(int64_t));
+  std::memcpy(key.data() + f.size() * sizeof(int64_t), data, total);
+  return key;
 }
 
 // Flops and algorithmic bytes of one pass; a controlled pass with c controls
@@ -184,18 +210,61 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
     ++i;
   }
   if (total == 0) return;
-  drop_graph(s);
   const size_t base = arena_take(s, total);
   for (size_t i = 0; i < passes.size(); ++i) {
-    passes[i].mat_off += base;
-    unsigned char* dst = s->arena_host + passes[i].mat_off;
+    unsigned char* dst = s->arena_host + base + passes[i].mat_off;
     if (passes[i].variant == V_PHASE) std::memcpy(dst, phase_data[i].data(), passes[i].mat_bytes);
     else encode_pass_data(passes[i], mats[i], dst);
   }
-  SV_HIP(hipMemcpyAsync(s->arena_dev + base, s->arena_host + base, total, hipMemcpyHostToDevice, s->stream));
-  if (stats) SV_HIP(hipEventRecord(s->ev0, s->stream));
   const bool timing = o.timing && stats;
-  const bool graph = o.use_graph && s->stream != nullptr && !timing;
+  const bool graph = o.use_graph && !timing;
+  if (graph) {
+    // The graph reads its pass data from its own buffer, so ring uploads of
+    // later calls never disturb it; relaunch when nothing it encodes changed.
+    std::vector<unsigned char> key = graph_key(passes, s->arena_host + base, total);
+    const bool relaunch = s->graph_exec && key == s->graph_key;
+    if (stats) stats->graph_relaunched = relaunch ? 1 : 0;
+    if (!relaunch) {
+      drop_graph(s);
+      if (total > s->graph_cap) {
+        SV_HIP(hipStreamSynchronize(s->stream));
+        if (s->graph_dev) SV_HIP(hipFree(s->graph_dev));
+        s->graph_dev = nullptr;
+        s->graph_cap = 0;
+        SV_HIP(hipMalloc(&s->graph_dev, total));
+        s->graph_cap = total;
+      }
+      SV_HIP(hipMemcpyAsync(s->graph_dev, s->arena_host + base, total, hipMemcpyHostToDevice, s->stream));
+      // Capture records without executing, so a private stream serves any
+      // caller stream, the legacy null stream included.
+      if (!s->capture_stream) SV_HIP(hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking));
+      hipStream_t cs = s->capture_stream;
+      SV_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      try {
+        for (const Pass& p : passes) launch_pass(p, s->n, s->psi, s->graph_dev, cs);
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(cs, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      hipGraph_t g = nullptr;
+      SV_HIP(hipStreamEndCapture(cs, &g));
+      hipError_t e = hipGraphInstantiate(&s->graph_exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        s->graph_exec = nullptr;
+        throw DeviceError{e, "hipGraphInstantiate"};
+      }
+      s->graph_key = std::move(key);
+    }
+    if (stats) SV_HIP(hipEventRecord(s->ev0, s->stream));
+    SV_HIP(hipGraphLaunch(s->graph_exec, s->stream));
+  } else {
+    for (Pass& p : passes) p.mat_off += base;
+    SV_HIP(hipMemcpyAsync(s->arena_dev + base, s->arena_host + base, total, hipMemcpyHostToDevice, s->stream));
+    if (stats) SV_HIP(hipEventRecord(s->ev0, s->stream));
+  }
   if (timing) {
     while (s->pass_events.size() < passes.size() + 1) {
       hipEvent_t e;
@@ -207,23 +276,7 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
       launch_pass(passes[i], s->n, s->psi, s->arena_dev, s->stream);
       SV_HIP(hipEventRecord(s->pass_events[i + 1], s->stream));
     }
-  } else if (graph) {
-    SV_HIP(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-    try {
-      for (const Pass& p : passes) launch_pass(p, s->n, s->psi, s->arena_dev, s->stream);
-    } catch (...) {
-      hipGraph_t g = nullptr;
-      (void)hipStreamEndCapture(s->stream, &g);
-      if (g) (void)hipGraphDestroy(g);
-      throw;
-    }
-    hipGraph_t g = nullptr;
-    SV_HIP(hipStreamEndCapture(s->stream, &g));
-    hipError_t e = hipGraphInstantiate(&s->graph_exec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) throw DeviceError{e, "hipGraphInstantiate"};
-    SV_HIP(hipGraphLaunch(s->graph_exec, s->stream));
-  } else {
+  } else if (!graph) {
     for (const Pass& p : passes) launch_pass(p, s->n, s->psi, s->arena_dev, s->stream);
   }
   if (stats) {
@@ -333,6 +386,14 @@ extern "C" {
 
 const char* sv_last_error(void) { return g_last_error.c_str(); }
 const char* sv_version(void) { return "libsv 0.1.0 (gfx950)"; }
+size_t sv_struct_size(int which) {
+  switch (which) {
+    case 0: return sizeof(sv_gate);
+    case 1: return sizeof(sv_run_opts);
+    case 2: return sizeof(sv_run_stats);
+    default: return 0;
+  }
+}
 
 int sv_alloc(int n_qubits, int dtype, void* dev_buf, size_t buf_bytes, void* hip_stream, sv_state** out) {
   if (!out) return fail(SV_EINVAL, "out is NULL");
@@ -381,6 +442,8 @@ int sv_free(sv_state* s) {
   (void)hipSetDevice(s->device);
   (void)hipStreamSynchronize(s->stream);
   if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+  if (s->graph_dev) (void)hipFree(s->graph_dev);
+  if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
   if (s->arena_dev) (void)hipFree(s->arena_dev);
   if (s->arena_host) (void)hipHostFree(s->arena_host);
   if (s->partials) (void)hipFree(s->partials);

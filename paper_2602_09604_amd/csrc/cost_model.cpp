@@ -16,6 +16,7 @@
 //     cost plus alpha times the cost of running the gate as a pass of its own,
 //     for several alpha.
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <exception>
@@ -40,6 +41,14 @@ namespace {
 
 constexpr int F = SV_COST_FEATURES;
 constexpr double kLaunchOverheadNs = 4000.0;
+// beam searches over largest-block passes: partial partitions kept per pass
+// (two widths; the search is not monotone in it), candidate sets tried per
+// partial partition, and the largest circuit searched
+constexpr int kBeamWidths[2] = {32, 64};
+constexpr int kBeamMoves = 8;
+constexpr size_t kBeamMaxGates = (size_t)1 << 14;
+// predicted saving a partition with more passes needs over the fewest-pass one
+constexpr double kFewerPassMargin = 0.05;
 
 std::mutex g_mu;
 std::vector<float> g_params;
@@ -161,8 +170,11 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
       }
     });
   };
-  for (int K = max_k; K >= 1 && K >= max_k - 1; --K)
-    for (bool narrow : {false, true}) blk.push_back({});
+  // broad and narrow rule at max_k and max_k - 1, then the beam searches; sized
+  // before any thread starts so that the slots never move
+  for (int K = max_k; K >= 1 && K >= max_k - 1; --K) blk.resize(blk.size() + 2);
+  const bool beam = n <= kBeamMaxGates;
+  if (beam) blk.resize(blk.size() + 2);
   {
     size_t i = 0;
     for (int K = max_k; K >= 1 && K >= max_k - 1; --K)
@@ -170,6 +182,11 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
         std::vector<std::vector<int>>* dst = &blk[i++];
         spawn([=] { maxblock_partition(g, n, K, narrow, *dst); });
       }
+  }
+  for (int w = 0; beam && w < 2; ++w) {  // beam searches over largest-block passes at max_k
+    std::vector<std::vector<int>>* dst = &blk[blk.size() - 2 + w];
+    const int width = kBeamWidths[w];
+    spawn([=] { beam_partition(g, n, max_k, width, kBeamMoves, *dst); });
   }
   std::vector<FusedGate> ph;
   std::vector<int32_t> ph_of;
@@ -181,15 +198,26 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
         if (t.joinable()) t.join();
     }
   } joiner{pool};
-  std::vector<std::vector<int>> best, cand;
-  double best_t = 1e300;
-  for (int K = 1; K <= max_k; ++K) {
-    greedy_partition(g, n, K, cand);
-    const double t = total(cand);
+  // The predicted-cheapest candidate and the candidate with the fewest passes
+  // (the cheaper of those on ties) are both tracked; see the choice below.
+  std::vector<std::vector<int>> best, fewest, cand;
+  double best_t = 1e300, fewest_t = 1e300;
+  size_t fewest_n = SIZE_MAX;
+  auto consider = [&](const std::vector<std::vector<int>>& c) {
+    const double t = total(c);
     if (t < best_t) {
       best_t = t;
-      best = cand;
+      best = c;
     }
+    if (c.size() < fewest_n || (c.size() == fewest_n && t < fewest_t)) {
+      fewest_n = c.size();
+      fewest_t = t;
+      fewest = c;
+    }
+  };
+  for (int K = 1; K <= max_k; ++K) {
+    greedy_partition(g, n, K, cand);
+    consider(cand);
   }
   for (double alpha : {0.25, 0.5, 1.0}) {
     if (!model) break;  // the cost-aware variants need predicted times
@@ -200,41 +228,51 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
           return pass_ns(S2) - pass_ns(S) <= alpha * pass_ns(qh);
         },
         cand);
-    const double t = total(cand);
-    if (t < best_t) {
-      best_t = t;
-      best = cand;
-    }
+    consider(cand);
   }
-  // The phase-block partition: each run of phase gates is one elementwise
-  // sweep, priced as a one-qubit pass on the top qubit (same traffic, no gather).
   for (auto& t : pool) t.join();
   if (!errs.empty()) std::rethrow_exception(errs.front());
-  for (auto& b : blk) {  // largest-block partitions, in the order they were started
-    const double t = total(b);
-    if (t < best_t) {
-      best_t = t;
-      best = b;
-    }
-  }
+  for (auto& b : blk) consider(b);  // largest-block partitions, in the order they were started
+  // The phase-block partition: each run of phase gates is one elementwise
+  // sweep, priced as a one-qubit pass on the top qubit (same traffic, no gather).
   double t_ph = 0;
+  size_t n_ph = 0;
   bool in_run = false;
   for (const FusedGate& f : ph) {
     if (!f.cmask && is_phase_matrix(f.k, f.mat.data())) {
-      if (!in_run) t_ph += pass_ns((uint64_t)1 << (n_qubits - 1));
+      if (!in_run) {
+        t_ph += pass_ns((uint64_t)1 << (n_qubits - 1));
+        ++n_ph;
+      }
       in_run = true;
     } else {
       in_run = false;
       uint64_t m = 0;
       for (int j = 0; j < f.k; ++j) m |= (uint64_t)1 << f.q[j];
       t_ph += f.cmask ? ctrl_ns(m, f.cmask) : pass_ns(m);
+      ++n_ph;
     }
   }
-  if (t_ph < best_t) {
+  // Every pass moves the whole state, so a partition with more passes is only
+  // taken when the model predicts it clearly cheaper than the fewest-pass one:
+  // the argmin over many candidates otherwise tends to pick the one whose
+  // passes the model happens to under-predict.
+  const bool phase_best = t_ph < best_t;
+  const double chosen_t = phase_best ? t_ph : best_t;
+  const size_t chosen_n = phase_best ? n_ph : best.size();
+  const bool phase_fewest = n_ph < fewest_n || (n_ph == fewest_n && t_ph < fewest_t);
+  if (phase_fewest) {
+    fewest_n = n_ph;
+    fewest_t = t_ph;
+  }
+  const bool keep_fewest = model && chosen_n > fewest_n && chosen_t > (1.0 - kFewerPassMargin) * fewest_t;
+  const bool use_phase = keep_fewest ? phase_fewest : phase_best;
+  if (use_phase) {
     out = std::move(ph);
     block_of = std::move(ph_of);
     return true;
   }
+  if (keep_fewest) best.swap(fewest);
   fuse_blocks(g, n, best, out, block_of);
   return true;
 }

@@ -20,9 +20,12 @@
 // blocks all of its qubits, controls included, for every other block.
 #include <algorithm>
 #include <atomic>
+#include <condition_variable>
 #include <cstring>
 #include <exception>
 #include <functional>
+#include <memory>
+#include <mutex>
 #include <thread>
 #include <unordered_map>
 
@@ -294,26 +297,79 @@ struct BlockSearch {
 };
 }  // namespace
 
-void maxblock_partition(const sv_gate* g, size_t n, int max_k, bool narrow, std::vector<std::vector<int>>& blocks) {
-  blocks.clear();
-  BlockSearch b;
+namespace {
+// The first remaining gate on each of its qubits.
+std::vector<int> front_of(const BlockSearch& b) {
+  std::vector<int> front;
+  uint64_t blocked = 0;
+  for (int h : b.live) {
+    if ((b.masks[h] & blocked) == 0) front.push_back(h);
+    blocked |= b.masks[h];
+  }
+  return front;
+}
+
+// Grow a candidate set from front gate f (the growth described above);
+// returns the best (count, set) seen along the way.  count_of evaluates and
+// memoises absorbed-gate counts.
+template <class CountOf>
+std::pair<int, uint64_t> grow_from(const BlockSearch& b, const std::vector<int>& front, int f, int max_k,
+                                   CountOf&& count_of, std::vector<uint64_t>& adds) {
+  uint64_t S = b.masks[f];
+  int seen = count_of(S);
+  uint64_t seen_S = S;
+  while (true) {
+    // additions: the outside qubits of a gate that touches S, or a whole
+    // front gate elsewhere (horizontal fusion)
+    adds.clear();
+    b.absorb(S, nullptr, &adds);
+    for (int f2 : front)
+      if (!b.g[f2].cmask && (b.masks[f2] & ~S)) adds.push_back(b.masks[f2] & ~S);
+    std::sort(adds.begin(), adds.end());
+    adds.erase(std::unique(adds.begin(), adds.end()), adds.end());
+    int step_count = -1, step_bits = 0;
+    uint64_t step_S = 0;
+    for (uint64_t add : adds) {
+      const uint64_t S2 = S | add;
+      const int bits = __builtin_popcountll(S2);
+      if (bits > max_k) continue;
+      const int c = count_of(S2);
+      if (c > step_count || (c == step_count && bits < step_bits)) {
+        step_count = c;
+        step_bits = bits;
+        step_S = S2;
+      }
+    }
+    if (step_count < 0) break;
+    S = step_S;
+    if (step_count > seen) {
+      seen = step_count;
+      seen_S = S;
+    }
+  }
+  return {seen, seen_S};
+}
+
+void init_search(BlockSearch& b, const sv_gate* g, size_t n) {
   b.g = g;
-  b.narrow = narrow;
   b.masks.resize(n);
+  b.live.clear();
   for (size_t i = 0; i < n; ++i) {
     b.masks[i] = qmask(g[i]);
     b.live.push_back((int)i);
   }
+}
+}  // namespace
+
+void maxblock_partition(const sv_gate* g, size_t n, int max_k, bool narrow, std::vector<std::vector<int>>& blocks) {
+  blocks.clear();
+  BlockSearch b;
+  init_search(b, g, n);
+  b.narrow = narrow;
   std::vector<char> done(n, 0);
   std::vector<uint64_t> adds;
   while (!b.live.empty()) {
-    // the front: the first remaining gate on each of its qubits
-    std::vector<int> front;
-    uint64_t blocked = 0;
-    for (int h : b.live) {
-      if ((b.masks[h] & blocked) == 0) front.push_back(h);
-      blocked |= b.masks[h];
-    }
+    const std::vector<int> front = front_of(b);
     std::vector<int> chosen;
     for (int f : front)
       if (g[f].cmask) {  // a wide controlled gate: its own pass
@@ -333,41 +389,10 @@ void maxblock_partition(const sv_gate* g, size_t n, int max_k, bool narrow, std:
       };
       for (int f : front) {
         if (g[f].cmask) continue;
-        uint64_t S = b.masks[f];
-        int seen = count_of(S);
-        uint64_t seen_S = S;
-        while (true) {
-          // additions: the outside qubits of a gate that touches S, or a
-          // whole front gate elsewhere (horizontal fusion)
-          adds.clear();
-          b.absorb(S, nullptr, &adds);
-          for (int f2 : front)
-            if (!g[f2].cmask && (b.masks[f2] & ~S)) adds.push_back(b.masks[f2] & ~S);
-          std::sort(adds.begin(), adds.end());
-          adds.erase(std::unique(adds.begin(), adds.end()), adds.end());
-          int step_count = -1, step_bits = 0;
-          uint64_t step_S = 0;
-          for (uint64_t add : adds) {
-            const uint64_t S2 = S | add;
-            const int bits = __builtin_popcountll(S2);
-            if (bits > max_k) continue;
-            const int c = count_of(S2);
-            if (c > step_count || (c == step_count && bits < step_bits)) {
-              step_count = c;
-              step_bits = bits;
-              step_S = S2;
-            }
-          }
-          if (step_count < 0) break;
-          S = step_S;
-          if (step_count > seen) {
-            seen = step_count;
-            seen_S = S;
-          }
-        }
-        if (seen > best_count) {
-          best_count = seen;
-          best_S = seen_S;
+        const auto r = grow_from(b, front, f, max_k, count_of, adds);
+        if (r.first > best_count) {
+          best_count = r.first;
+          best_S = r.second;
         }
       }
       b.absorb(best_S, &chosen, nullptr);
@@ -379,6 +404,199 @@ void maxblock_partition(const sv_gate* g, size_t n, int max_k, bool narrow, std:
       if (!done[h]) rest.push_back(h);
     b.live.swap(rest);
     blocks.push_back(std::move(chosen));
+  }
+}
+
+// Beam search over largest-block passes.  A partial partition is ranked by
+// the gates it leaves; each one is extended by the `topm` sets that absorb the
+// most gates among all the sets the growth search evaluates (more absorbed
+// first, then fewer qubits, then the smaller mask), and after every pass the
+// `width` best distinct partial partitions are kept.  The first to absorb the
+// whole circuit is returned, so it has the fewest passes the beam found.  The
+// partial partitions of a pass are extended on host threads; the result does
+// not depend on how many.
+namespace {
+struct BeamChain {  // the passes of a partial partition, last first
+  std::vector<int> block;
+  std::shared_ptr<const BeamChain> prev;
+};
+struct BeamNode {
+  std::vector<int> live;
+  std::shared_ptr<const BeamChain> passes;
+};
+
+void beam_expand(BlockSearch& b, const BeamNode& nd, int max_k, int topm, std::vector<uint64_t>& adds,
+                 std::vector<char>& taken, std::vector<BeamNode>& kids) {
+  b.live = nd.live;
+  const std::vector<int> front = front_of(b);
+  std::vector<uint64_t> moves;  // candidate sets; 0 stands for a controlled front gate
+  int ctrl = -1;
+  for (int f : front)
+    if (b.g[f].cmask) {
+      ctrl = f;
+      break;
+    }
+  if (ctrl < 0) {
+    std::unordered_map<uint64_t, int> memo;
+    auto count_of = [&](uint64_t S) {
+      auto it = memo.find(S);
+      if (it != memo.end()) return it->second;
+      const int c = b.absorb(S, nullptr, nullptr);
+      memo.emplace(S, c);
+      return c;
+    };
+    for (int f : front) (void)grow_from(b, front, f, max_k, count_of, adds);
+    std::vector<std::pair<int, uint64_t>> ranked;
+    ranked.reserve(memo.size());
+    for (const auto& kv : memo) ranked.push_back({kv.second, kv.first});
+    std::sort(ranked.begin(), ranked.end(), [](const std::pair<int, uint64_t>& x, const std::pair<int, uint64_t>& y) {
+      if (x.first != y.first) return x.first > y.first;
+      const int bx = __builtin_popcountll(x.second), by = __builtin_popcountll(y.second);
+      if (bx != by) return bx < by;
+      return x.second < y.second;
+    });
+    for (size_t i = 0; i < ranked.size() && (int)moves.size() < topm; ++i)
+      if (ranked[i].first > 0) moves.push_back(ranked[i].second);
+  } else {
+    moves.push_back(0);
+  }
+  for (uint64_t S : moves) {
+    BeamNode child;
+    std::vector<int> chosen;
+    if (S == 0) chosen.push_back(ctrl);
+    else b.absorb(S, &chosen, nullptr);
+    for (int h : chosen) taken[h] = 1;
+    child.live.reserve(b.live.size() - chosen.size());
+    for (int h : b.live)
+      if (!taken[h]) child.live.push_back(h);
+    for (int h : chosen) taken[h] = 0;
+    child.passes = std::make_shared<const BeamChain>(BeamChain{std::move(chosen), nd.passes});
+    kids.push_back(std::move(child));
+  }
+}
+
+// Host threads kept for a whole search: run() wakes every worker for one
+// round of body(w) (the caller runs body(0)) and returns when all are done.
+// body must not throw.
+class RoundPool {
+ public:
+  RoundPool(unsigned threads, std::function<void(unsigned)> body) : body_(std::move(body)) {
+    try {
+      for (unsigned w = 1; w < threads; ++w) threads_.emplace_back([this, w] { loop(w); });
+    } catch (...) {
+      shutdown();
+      throw;
+    }
+  }
+  ~RoundPool() { shutdown(); }
+  void run() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      ++round_;
+      busy_ = (unsigned)threads_.size();
+    }
+    wake_.notify_all();
+    body_(0);
+    std::unique_lock<std::mutex> lk(mu_);
+    idle_.wait(lk, [&] { return busy_ == 0; });
+  }
+
+ private:
+  void loop(unsigned w) {
+    uint64_t seen = 0;
+    while (true) {
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        wake_.wait(lk, [&] { return stop_ || round_ != seen; });
+        if (stop_) return;
+        seen = round_;
+      }
+      body_(w);
+      std::lock_guard<std::mutex> lk(mu_);
+      if (--busy_ == 0) idle_.notify_one();
+    }
+  }
+  void shutdown() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    wake_.notify_all();
+    for (auto& t : threads_) t.join();
+    threads_.clear();
+  }
+  std::function<void(unsigned)> body_;
+  std::vector<std::thread> threads_;
+  std::mutex mu_;
+  std::condition_variable wake_, idle_;
+  uint64_t round_ = 0;
+  unsigned busy_ = 0;
+  bool stop_ = false;
+};
+}  // namespace
+
+void beam_partition(const sv_gate* g, size_t n, int max_k, int width, int topm,
+                    std::vector<std::vector<int>>& blocks) {
+  blocks.clear();
+  if (n == 0) return;
+  width = std::max(width, 1);
+  topm = std::max(topm, 1);
+  BlockSearch proto;
+  init_search(proto, g, n);
+  std::vector<BeamNode> beam(1);
+  beam[0].live = proto.live;
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const unsigned nt = host_pool_worker() ? 1u : (unsigned)std::min<size_t>(hw, width);
+  std::vector<std::vector<BeamNode>> kids;
+  std::atomic<size_t> next{0};
+  std::vector<std::exception_ptr> errs(nt);
+  std::vector<BlockSearch> search(nt, proto);
+  RoundPool pool(nt, [&](unsigned w) {
+    try {
+      std::vector<uint64_t> adds;
+      std::vector<char> taken(n, 0);
+      for (size_t i = next++; i < beam.size(); i = next++)
+        beam_expand(search[w], beam[i], max_k, topm, adds, taken, kids[i]);
+    } catch (...) {  // carried back to the caller; an exception must not end a thread
+      errs[w] = std::current_exception();
+      next = beam.size();
+    }
+  });
+  while (true) {
+    kids.assign(beam.size(), {});
+    next = 0;
+    pool.run();
+    for (auto& e : errs)
+      if (e) std::rethrow_exception(e);
+    std::vector<BeamNode> cand;
+    for (auto& ks : kids)
+      for (auto& c : ks) {
+        if (c.live.empty()) {  // the first complete partition, in beam order
+          for (const BeamChain* p = c.passes.get(); p; p = p->prev.get()) blocks.push_back(p->block);
+          std::reverse(blocks.begin(), blocks.end());
+          return;
+        }
+        cand.push_back(std::move(c));
+      }
+    std::stable_sort(cand.begin(), cand.end(),
+                     [](const BeamNode& x, const BeamNode& y) { return x.live.size() < y.live.size(); });
+    beam.clear();
+    std::unordered_map<uint64_t, std::vector<size_t>> seen;  // hash of the remaining gates -> kept nodes
+    for (BeamNode& c : cand) {
+      if ((int)beam.size() >= width) break;
+      uint64_t h = 1469598103934665603ull;
+      for (int v : c.live) h = (h ^ (uint64_t)v) * 1099511628211ull;
+      auto& bucket = seen[h];
+      bool dup = false;
+      for (size_t j : bucket)
+        if (beam[j].live == c.live) {
+          dup = true;
+          break;
+        }
+      if (dup) continue;
+      bucket.push_back(beam.size());
+      beam.push_back(std::move(c));
+    }
   }
 }
 

@@ -94,10 +94,10 @@ void launch_kl(float4* psi, const float2* U, const ShflArgs& a, uint64_t elems, 
 // of the wavefront, bit 6, costs more permute bandwidth than it saves).
 bool shfl_eligible(int n, int k, const int* s) {
   if (n < 9 || k < 1 || k > 3) return false;
-  int lane = 0, zero = 0, top = 0;
+  int lane = 0, top = 0;
   for (int j = 0; j < k; ++j) {
-    if (s[j] == 0) ++zero;
-    else if (s[j] <= 6) ++lane, top = s[j] > top ? s[j] : top;
+    if (s[j] == 0) continue;
+    if (s[j] <= 6) ++lane, top = s[j] > top ? s[j] : top;
     else return false;
   }
   if (lane == 0 || (lane >= 2 && top > 5)) return false;

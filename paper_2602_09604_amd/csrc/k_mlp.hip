@@ -37,7 +37,6 @@ namespace {
 
 constexpr int F = SV_COST_FEATURES;
 constexpr int CH = 64;  // samples per workgroup
-constexpr int WMAX = 64;
 
 int num_params(int w) { return w * F + w + w * w + w + w + 1; }
 

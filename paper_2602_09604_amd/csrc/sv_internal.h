@@ -124,6 +124,8 @@ void fuse_none(const sv_gate* g, size_t n, std::vector<FusedGate>& out, std::vec
 void fuse_maxblock(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>& out,
                    std::vector<int32_t>& block_of);
 void maxblock_partition(const sv_gate* g, size_t n, int max_k, bool narrow, std::vector<std::vector<int>>& blocks);
+void beam_partition(const sv_gate* g, size_t n, int max_k, int width, int topm,
+                    std::vector<std::vector<int>>& blocks);
 void fuse_blocks(const sv_gate* g, size_t n, const std::vector<std::vector<int>>& blocks,
                  std::vector<FusedGate>& out, std::vector<int32_t>& block_of);
 // Set on threads of a host worker pool so that the work they call does not

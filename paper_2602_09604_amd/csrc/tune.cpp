@@ -128,7 +128,7 @@ int sv_autotune(sv_state* s, int budget_ms) {
             int c = 0;
             if (q0) p.s[c++] = 0;
             for (int i = 0; i < nlow; ++i) p.s[c++] = 1 + i;
-            for (int i = 0; c < k; ++i) p.s[c++] = n - (k - c);
+            for (; c < k; ++c) p.s[c] = n - k + c;  // the rest on the top qubits
             std::sort(p.s, p.s + k);
             std::vector<std::pair<int, int>> cands = {{V_REG, 12}, {V_LDS, 10}, {V_LDS, 12}};
             if (mfma_supported(k, prec) && n >= k + 6) cands.push_back({V_MFMA, 12});

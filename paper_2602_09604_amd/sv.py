@@ -50,7 +50,8 @@ class sv_run_opts(ctypes.Structure):
 class sv_run_stats(ctypes.Structure):
     _fields_ = [("gates_in", ctypes.c_uint64), ("passes", ctypes.c_uint64), ("bytes", ctypes.c_uint64),
                 ("useful_flops", ctypes.c_double), ("fuse_s", ctypes.c_double), ("gpu_s", ctypes.c_double),
-                ("variant_s", ctypes.c_double * 5), ("variant_passes", ctypes.c_uint64 * 5)]
+                ("variant_s", ctypes.c_double * 5), ("variant_passes", ctypes.c_uint64 * 5),
+                ("graph_relaunched", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -107,6 +108,7 @@ _SIGS = {
     "sv_cost_features": (ctypes.c_int, [ctypes.c_int, _i32p, ctypes.c_int, ctypes.c_int, _fp]),
     "sv_last_error": (ctypes.c_char_p, []),
     "sv_version": (ctypes.c_char_p, []),
+    "sv_struct_size": (ctypes.c_size_t, [ctypes.c_int]),
 }
 
 
@@ -122,6 +124,10 @@ def lib():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        for which, struct in enumerate((sv_gate, sv_run_opts, sv_run_stats)):
+            if L.sv_struct_size(which) != ctypes.sizeof(struct):
+                raise RuntimeError("%s layout differs from libsv.so (%d vs %d bytes); rebuild the library"
+                                   % (struct.__name__, ctypes.sizeof(struct), L.sv_struct_size(which)))
         _lib = L
     return _lib
 
@@ -406,6 +412,11 @@ def sv_cost_features(k: int, qubits, n: int, precision: int) -> np.ndarray:
     out = np.zeros(SV_COST_FEATURES, dtype=np.float32)
     _check(lib().sv_cost_features(k, q.ctypes.data_as(_i32p), n, precision, out.ctypes.data_as(_fp)))
     return out
+
+
+def sv_struct_size(which: int) -> int:
+    """sizeof(sv_gate), sizeof(sv_run_opts), sizeof(sv_run_stats) for which 0, 1, 2."""
+    return int(lib().sv_struct_size(which))
 
 
 # --------------------------------------------------------------------------

@@ -235,3 +235,44 @@ def test_learned_without_model_keeps_fewest_passes():
     fused, _ = sv.sv_fuse(gates, n, sv.make_opts(max_k=5, fusion="learned"))
     ref = oracle.apply_circuit(n, gates)
     assert np.max(np.abs(oracle.apply_circuit(n, fused) - ref)) < 1e-12
+
+
+@needs_lib
+@pytest.mark.parametrize("case", ["random8_k5", "random12_k3", "grid4x3_k6"])
+def test_beam_search_finds_fewer_passes(case):
+    """Learned fusion without a model includes a beam search over
+    largest-block passes; on these circuits it needs one pass fewer than the
+    largest-block rule, and its partition reaches the unfused state."""
+    from paper_2602_09604_amd import costmodel  # noqa: F401  (no model is installed in the CPU suite)
+    n, max_k, gates = {
+        "random8_k5": (8, 5, lambda: C.random_circuit(8, 150, max_k=2, seed=5)),
+        "random12_k3": (12, 3, lambda: C.random_circuit(12, 150, max_k=2, seed=4)),
+        "grid4x3_k6": (12, 6, lambda: C.grid_circuit(4, 3, 30, seed=0)),
+    }[case]
+    gates = gates()
+    block, _ = sv.sv_fuse(gates, n, sv.make_opts(max_k=max_k, fusion="block"))
+    fused, block_of = sv.sv_fuse(gates, n, sv.make_opts(max_k=max_k, fusion="learned"))
+    _check_partition(gates, fused, block_of, max_k)
+    assert len(fused) < len(block), (len(fused), len(block))
+    ref = oracle.apply_circuit(n, gates, init=3)
+    assert np.max(np.abs(oracle.apply_circuit(n, fused, init=3) - ref)) < 1e-12
+
+
+@needs_lib
+def test_beam_search_on_34_qubit_grid():
+    """The 2x17 depth-24 grid: the beam search takes it from 53 largest-block
+    passes to at most 50, with a valid partition."""
+    gates = C.grid_circuit(2, 17, 24, seed=0)
+    fused, block_of = sv.sv_fuse(gates, 34, sv.make_opts(max_k=6, fusion="learned"))
+    _check_partition(gates, fused, block_of, 6)
+    assert len(fused) <= 50, len(fused)
+
+
+def test_struct_layouts_match_binding():
+    """The ctypes mirrors of the ABI structs have the library's sizes."""
+    from paper_2602_09604_amd import sv
+    import ctypes
+    assert sv.sv_struct_size(0) == ctypes.sizeof(sv.sv_gate)
+    assert sv.sv_struct_size(1) == ctypes.sizeof(sv.sv_run_opts)
+    assert sv.sv_struct_size(2) == ctypes.sizeof(sv.sv_run_stats)
+    assert sv.sv_struct_size(3) == 0 and sv.sv_struct_size(-1) == 0

@@ -63,6 +63,32 @@ def test_learned_fusion_with_constant_model_is_valid(tmp_path):
     assert np.max(np.abs(oracle.apply_circuit(n, fused) - ref)) < 1e-12
 
 
+def test_high_target_augmentation():
+    """Copies keep the label, k, the precision and n features and every
+    target below bit 13; high targets move to distinct bits in [13, 34)."""
+    from paper_2602_09604_amd import costmodel
+    rng = np.random.Generator(np.random.PCG64(3))
+    X = np.zeros((50, 40), dtype=np.float32)
+    y = rng.standard_normal(50).astype(np.float32)
+    for i in range(50):
+        k = int(rng.integers(1, 7))
+        X[i, 0], X[i, 1] = k / 6.0, 30 / 34.0
+        X[i, 2 + rng.permutation(30)[:k]] = 1.0
+        X[i, 36 + int(rng.integers(4))] = 1.0
+    Xa, ya = costmodel.augment_high_targets(X, y, 3, np.random.Generator(np.random.PCG64(4)))
+    assert Xa.shape == (200, 40) and np.array_equal(Xa[:50], X)
+    moved = 0
+    for c in range(1, 4):
+        Xc, yc = Xa[50 * c:50 * (c + 1)], ya[50 * c:50 * (c + 1)]
+        assert np.array_equal(yc, y)
+        assert np.array_equal(Xc[:, :2], X[:, :2]) and np.array_equal(Xc[:, 36:], X[:, 36:])
+        assert np.array_equal(Xc[:, 2:15], X[:, 2:15])  # bits 0..12 untouched
+        assert np.array_equal(Xc[:, 2:36].sum(1), X[:, 2:36].sum(1))  # same number of targets
+        assert set(np.unique(Xc)) <= {0.0, 1.0} | set(np.unique(X[:, :2]))
+        moved += int(np.sum(Xc[:, 2 + 30:36]))  # bits 30..33 were never set in X
+    assert moved > 0
+
+
 @pytest.mark.gpu
 def test_corpus_training_and_learned_partition():
     import torch

@@ -99,6 +99,40 @@ def test_config1_grid_unfused_full_state():
         say(r)
 
 
+@pytest.mark.parametrize("own_stream", [False, True])
+def test_graph_relaunch_and_replacement(own_stream):
+    """use_graph keeps its graph: the same circuit again relaunches it, plain
+    calls in between (which reuse the upload ring) leave its pass data alone,
+    and a different circuit replaces it.  The state after the whole sequence
+    matches the oracle, on the default stream and on a stream of its own."""
+    import torch
+    sv = _sv()
+    n = 14
+    a = random_state_circuit(n, 3) + C.random_circuit(n, 40, max_k=3, seed=21)
+    b = C.random_circuit(n, 30, max_k=2, seed=22)
+    arrays = {"a": sv.GateArray(a), "b": sv.GateArray(b)}
+    runs = [("a", dict(max_k=5, fusion="greedy", precision="fp16x3", use_graph=True), 0),
+            ("a", dict(max_k=5, fusion="greedy", precision="fp16x3", use_graph=True), 1),
+            ("b", dict(max_k=4, fusion="phase"), None),
+            ("a", dict(max_k=5, fusion="greedy", precision="fp16x3", use_graph=True), 1),
+            ("a", dict(max_k=5, fusion="greedy", precision="fp32_valu", use_graph=True), 0),
+            ("b", dict(max_k=3, fusion="block", use_graph=True), 0),
+            ("b", dict(max_k=3, fusion="block", use_graph=True), 1),
+            ("a", dict(max_k=5, fusion="greedy", precision="fp16x3", use_graph=True), 0)]
+    st = sv.State(n, stream=torch.cuda.Stream() if own_stream else None)
+    try:
+        seq = []
+        for name, kw, relaunched in runs:
+            s = st.apply_circuit(arrays[name], stats=True, **kw)
+            say(name, kw, "relaunched", s["graph_relaunched"])
+            if relaunched is not None:
+                assert s["graph_relaunched"] == relaunched
+            seq += a if name == "a" else b
+        check(st.read(), oracle.apply_circuit(n, seq))
+    finally:
+        st.free()
+
+
 @pytest.mark.parametrize("max_k", [2, 3, 4, 5, 6])
 def test_grid_fused_greedy(max_k):
     n = 20

@@ -47,10 +47,12 @@ def workload(name: str):
     raise SystemExit("unknown workload " + name)
 
 
-def counter_traffic(kernel: str, workload_name: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when there is none or the kernel source has changed
-    since the counters were taken."""
+def counter_traffic(kernel: str, workload_name: str, alg_bytes_per_launch: float):
+    """HBM bytes per launch of `kernel`: the committed rocprofv3 counter
+    summary's ratio of measured to algorithmic bytes over that kernel's
+    launches, times this run's algorithmic bytes per launch; None when there
+    is no summary or the kernel source has changed since the counters were
+    taken."""
     import hashlib
     import re
     if kernel != "k_apply_mfma" or workload_name != "grid34":
@@ -62,11 +64,11 @@ def counter_traffic(kernel: str, workload_name: str):
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except OSError:
         return None
-    m = re.search(r"traffic_bytes_per_launch k_apply_mfma: ([0-9.e+]+)", text)
+    m = re.search(r"traffic_ratio k_apply_mfma: ([0-9.e+]+)", text)
     s = re.search(r"k_mfma.hip sha256: ([0-9a-f]+)", text)
     if not m or not s or s.group(1) != sha:
         return None
-    return float(m.group(1))
+    return float(m.group(1)) * alg_bytes_per_launch
 
 
 def run_step(st, gates, opts_kw, sample):
@@ -315,9 +317,9 @@ def main():
     if args.profile_step:
         # For hardware-counter runs: a copy of known size (8 GiB read + 8 GiB
         # written) to calibrate the byte counters, then one step of the
-        # circuit with the largest-block partition (no cost model is trained
-        # here; the per-dispatch bytes of a matrix-core pass do not depend on
-        # which partition produced it).
+        # circuit with learned fusion and no cost model (so the fewest state
+        # sweeps: blocks with controls, 2^c launches each over 2^-c of the
+        # state, as in the timed run).
         a = torch.empty(1 << 30, dtype=torch.complex64, device="cuda")
         b = torch.empty_like(a)
         b.copy_(a)
@@ -325,7 +327,7 @@ def main():
         del a, b
         torch.cuda.empty_cache()
         st = sv.State(n)
-        s = st.apply_circuit(gates, max_k=args.max_k, fusion="block", precision=args.precision, stats=True)
+        s = st.apply_circuit(gates, max_k=args.max_k, fusion="learned", precision=args.precision, stats=True)
         log("profile step: passes %d gpu %.3f s norm %.9f" % (s["passes"], s["gpu_s"], st.norm()))
         # the other pass kinds and the state reads, once each on the same state
         import numpy as np
@@ -384,24 +386,30 @@ def main():
             for v in range(5):
                 agg["variant_s"][v] += s["variant_s"][v]
                 agg["variant_passes"][v] += s["variant_passes"][v]
+                agg["variant_bytes"][v] += s["variant_bytes"][v]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall / args.steps * 1e3
     gates_per_s = len(gates) / (wall / args.steps)
     passes = agg["variant_passes"]
     dom = max(range(1, 5), key=lambda v: agg["variant_s"][v])
+    # launches differ in size when a block has controls (2^c launches, each
+    # over 2^-c of the state): per-launch figures are averages over the
+    # dominant kernel's launches, bytes / time over the same launches
     avg_launch = agg["variant_s"][dom] / max(1, passes[dom])
-    bytes_per_launch = 16.0 * (1 << n)
+    bytes_per_launch = agg["variant_bytes"][dom] / max(1, passes[dom])
     achieved = bytes_per_launch / avg_launch / 1e9
     pass_time = sum(agg["variant_s"][1:5])
     extra.update({
         "passes_per_step": int(sum(passes) / args.steps),
-        "alg_hbm_GBps_all_passes": sum(passes[1:5]) * bytes_per_launch / pass_time / 1e9,
+        "state_sweeps_per_step": sum(agg["variant_bytes"][1:5]) / args.steps / (16.0 * (1 << n)),
+        "alg_hbm_GBps_all_passes": sum(agg["variant_bytes"][1:5]) / pass_time / 1e9,
         "gpu_s_per_step": agg["gpu_s"] / args.steps,
         "fuse_s_per_step": agg["fuse_s"] / args.steps,
         "useful_tflops_per_s": agg["useful_flops"] / pass_time / 1e12,
         "norm_drift": max(abs(x - 1.0) for x in norms),
-        "per_variant": {VARIANT_NAMES[v]: {"passes": int(passes[v]), "avg_ms": 1e3 * agg["variant_s"][v] / passes[v]}
+        "per_variant": {VARIANT_NAMES[v]: {"passes": int(passes[v]), "avg_ms": 1e3 * agg["variant_s"][v] / passes[v],
+                                           "GBps": agg["variant_bytes"][v] / agg["variant_s"][v] / 1e9}
                         for v in range(1, 5) if passes[v]},
         "dominant_avg_launch_ms": 1e3 * avg_launch,
     })
@@ -460,7 +468,7 @@ def main():
                    "fusion": args.fusion, "max_k": args.max_k, "precision": args.precision},
         "roofline": {"bound": "hbm", "kernel": VARIANT_NAMES[dom], "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": counter_traffic(VARIANT_NAMES[dom], args.workload),
+                     "traffic": counter_traffic(VARIANT_NAMES[dom], args.workload, bytes_per_launch),
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "cpu_baseline": cpu,
         "extra": extra,

@@ -148,6 +148,7 @@ typedef struct {
   uint64_t variant_passes[5]; /* with opts.timing: passes per kernel family */
   uint64_t graph_relaunched;  /* 1 when opts.use_graph relaunched the handle's kept
                                  graph without capturing a new one */
+  uint64_t variant_bytes[5];  /* with opts.timing: algorithmic bytes per kernel family */
 } sv_run_stats;
 
 /* ---- state -------------------------------------------------------------- */

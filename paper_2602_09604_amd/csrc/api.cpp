@@ -188,9 +188,14 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
     p.precision = o.precision;
     p.cmask = fused[i].cmask;
     p.cval = fused[i].cval;
-    if (p.cmask) {  // controlled passes run on the register kernel family in FP32
-      p.precision = SV_PREC_FP32_VALU;
-      p.variant = V_REG;
+    if (p.cmask) {  // controlled passes: matrix cores when they take the controls, else registers in FP32
+      if (mfma_supported(p.k, o.precision) && mfma_ctrl_supported(s->n, p.k, p.cmask) &&
+          o.variant != SV_VARIANT_REG && o.variant != SV_VARIANT_LDS && o.variant != SV_VARIANT_SHFL) {
+        p.variant = V_MFMA;
+      } else {
+        p.precision = SV_PREC_FP32_VALU;
+        p.variant = V_REG;
+      }
       p.mat_bytes = pass_data_bytes(p);
       add(p);
       mats.push_back(fused[i].mat.data());
@@ -300,6 +305,7 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
         const int v = variant_family(passes[i].variant);
         stats->variant_s[v] += pm * 1e-3;
         stats->variant_passes[v] += 1;
+        stats->variant_bytes[v] += pass_bytes(s->n, passes[i]);
       }
     }
   }
@@ -328,7 +334,7 @@ static int check_opts(const sv_run_opts& o) {
 
 // Fuse per opts into `fused`.
 int plan_fusion(const sv_gate* g_in, size_t n, int n_qubits, const sv_run_opts& o, std::vector<FusedGate>& fused,
-                std::vector<int32_t>& block_of) {
+                std::vector<int32_t>& block_of, int max_ctrl) {
   // controlled gates narrow enough to fuse are lifted to dense gates first
   std::vector<sv_gate> lowered;
   std::vector<std::vector<double>> store;
@@ -346,7 +352,7 @@ int plan_fusion(const sv_gate* g_in, size_t n, int n_qubits, const sv_run_opts& 
   } else if (o.fusion == SV_FUSE_PHASE) {
     fuse_phase(g, n, o.max_k, fused, block_of);
   } else if (o.fusion == SV_FUSE_LEARNED) {
-    fuse_learned(g, n, n_qubits, o.max_k, o.precision, fused, block_of);
+    fuse_learned(g, n, n_qubits, o.max_k, o.precision, fused, block_of, max_ctrl);
   } else if (o.fusion == SV_FUSE_BLOCK) {
     fuse_maxblock(g, n, o.max_k, fused, block_of);
   } else {
@@ -534,7 +540,7 @@ int sv_apply_circuit(sv_state* s, const sv_gate* gates, size_t n_gates, const sv
   const auto t0 = std::chrono::steady_clock::now();
   std::vector<FusedGate> fused;
   std::vector<int32_t> block_of;
-  plan_fusion(gates, n_gates, s->n, o, fused, block_of);
+  plan_fusion(gates, n_gates, s->n, o, fused, block_of, s->n >= kBlockCtrlMinQubits ? kBlockCtrl : 0);
   const double fuse_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   run_passes(s, fused, o, stats);
   if (stats) {
@@ -558,7 +564,7 @@ int sv_fuse(const sv_gate* in, size_t n_in, int n_qubits, const sv_run_opts* opt
   try {
     std::vector<FusedGate> fused;
     std::vector<int32_t> block_of;
-    plan_fusion(in, n_in, n_qubits, o, fused, block_of);
+    plan_fusion(in, n_in, n_qubits, o, fused, block_of, n_qubits >= kBlockCtrlMinQubits ? kBlockCtrl : 0);
     // one allocation for the gate array, a second for all matrices
     size_t doubles = 0;
     for (auto& f : fused) doubles += f.mat.size();

@@ -34,8 +34,6 @@ void greedy_partition(const sv_gate* g, size_t n, int max_k, std::vector<std::ve
 void greedy_partition_cost(const sv_gate* g, size_t n, int max_k,
                            const std::function<bool(uint64_t, uint64_t, uint64_t)>& accept,
                            std::vector<std::vector<int>>& blocks);
-void fuse_blocks(const sv_gate* g, size_t n, const std::vector<std::vector<int>>& blocks,
-                 std::vector<FusedGate>& out, std::vector<int32_t>& block_of);
 
 namespace {
 
@@ -109,7 +107,7 @@ double cost_model_predict_log(int k, const int* qubits, int n, int precision) {
 }
 
 bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int precision, std::vector<FusedGate>& out,
-                  std::vector<int32_t>& block_of) {
+                  std::vector<int32_t>& block_of, int max_ctrl) {
   // Without a model every pass costs the same (it moves the same bytes): the
   // search then keeps the candidate with the fewest passes.
   const bool model = cost_model_ready();
@@ -135,16 +133,22 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
   auto ctrl_ns = [&](uint64_t targets, uint64_t cmask) {
     return pass_ns(targets) * std::ldexp(1.0, -__builtin_popcountll(cmask));
   };
-  auto total = [&](const std::vector<std::vector<int>>& blocks) {
+  // A block with c controls sweeps the state once, in 2^c launches on its
+  // targets, each over 2^-c of the state.
+  auto total = [&](const std::vector<std::vector<int>>& blocks, int ctrl) {
     double t = 0;
     for (auto& b : blocks) {
       if (b.size() == 1 && g[b[0]].cmask) {
         t += ctrl_ns(mask_of(b[0]), g[b[0]].cmask);
         continue;
       }
-      uint64_t m = 0;
-      for (int i : b) m |= mask_of(i);
-      t += pass_ns(m);
+      uint64_t S = 0, Cm = 0;
+      if (ctrl > 0) {
+        block_split(g, b, ctrl, S, Cm);
+      } else {
+        for (int i : b) S |= mask_of(i);
+      }
+      t += pass_ns(S) + (model ? ((1 << __builtin_popcountll(Cm)) - 1) * kLaunchOverheadNs : 0.0);
     }
     return t;
   };
@@ -152,7 +156,11 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
   // build; they are built on threads while the greedy candidates are scored.
   // (Inline, not on threads, when this search already runs on a pool worker.)
   const bool inline_only = host_pool_worker();
-  std::vector<std::vector<std::vector<int>>> blk;
+  struct Cand {
+    std::vector<std::vector<int>> blocks;
+    int ctrl = 0;  // controls a block may take
+  };
+  std::vector<Cand> blk;
   std::vector<std::thread> pool;
   std::vector<std::exception_ptr> errs;
   std::mutex err_mu;
@@ -170,23 +178,38 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
       }
     });
   };
-  // broad and narrow rule at max_k and max_k - 1, then the beam searches; sized
+  // broad and narrow rule at max_k and max_k - 1, then the beam searches,
+  // then (when controls are allowed) the same at max_k with controls; sized
   // before any thread starts so that the slots never move
-  for (int K = max_k; K >= 1 && K >= max_k - 1; --K) blk.resize(blk.size() + 2);
   const bool beam = n <= kBeamMaxGates;
-  if (beam) blk.resize(blk.size() + 2);
+  const int ctrl_rounds = max_ctrl > 0 ? 2 : 1;
+  for (int r = 0; r < ctrl_rounds; ++r) {
+    const int ctrl = r ? max_ctrl : 0;
+    for (int K = max_k; K >= 1 && K >= max_k - (r ? 0 : 1); --K)
+      for (int narrow = 0; narrow < 2; ++narrow) {
+        blk.emplace_back();
+        blk.back().ctrl = ctrl;
+      }
+    for (int w = 0; beam && w < 2; ++w) {
+      blk.emplace_back();
+      blk.back().ctrl = ctrl;
+    }
+  }
   {
     size_t i = 0;
-    for (int K = max_k; K >= 1 && K >= max_k - 1; --K)
-      for (bool narrow : {false, true}) {
-        std::vector<std::vector<int>>* dst = &blk[i++];
-        spawn([=] { maxblock_partition(g, n, K, narrow, *dst); });
+    for (int r = 0; r < ctrl_rounds; ++r) {
+      const int ctrl = r ? max_ctrl : 0;
+      for (int K = max_k; K >= 1 && K >= max_k - (r ? 0 : 1); --K)
+        for (int narrow = 0; narrow < 2; ++narrow) {
+          std::vector<std::vector<int>>* dst = &blk[i++].blocks;
+          spawn([=] { maxblock_partition(g, n, K, narrow != 0, *dst, ctrl); });
+        }
+      for (int w = 0; beam && w < 2; ++w) {  // beam searches over largest-block passes at max_k
+        std::vector<std::vector<int>>* dst = &blk[i++].blocks;
+        const int width = kBeamWidths[w];
+        spawn([=] { beam_partition(g, n, max_k, width, kBeamMoves, *dst, ctrl); });
       }
-  }
-  for (int w = 0; beam && w < 2; ++w) {  // beam searches over largest-block passes at max_k
-    std::vector<std::vector<int>>* dst = &blk[blk.size() - 2 + w];
-    const int width = kBeamWidths[w];
-    spawn([=] { beam_partition(g, n, max_k, width, kBeamMoves, *dst); });
+    }
   }
   std::vector<FusedGate> ph;
   std::vector<int32_t> ph_of;
@@ -201,23 +224,26 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
   // The predicted-cheapest candidate and the candidate with the fewest passes
   // (the cheaper of those on ties) are both tracked; see the choice below.
   std::vector<std::vector<int>> best, fewest, cand;
+  int best_ctrl = 0, fewest_ctrl = 0;
   double best_t = 1e300, fewest_t = 1e300;
   size_t fewest_n = SIZE_MAX;
-  auto consider = [&](const std::vector<std::vector<int>>& c) {
-    const double t = total(c);
+  auto consider = [&](const std::vector<std::vector<int>>& c, int ctrl) {
+    const double t = total(c, ctrl);
     if (t < best_t) {
       best_t = t;
       best = c;
+      best_ctrl = ctrl;
     }
     if (c.size() < fewest_n || (c.size() == fewest_n && t < fewest_t)) {
       fewest_n = c.size();
       fewest_t = t;
       fewest = c;
+      fewest_ctrl = ctrl;
     }
   };
   for (int K = 1; K <= max_k; ++K) {
     greedy_partition(g, n, K, cand);
-    consider(cand);
+    consider(cand, 0);
   }
   for (double alpha : {0.25, 0.5, 1.0}) {
     if (!model) break;  // the cost-aware variants need predicted times
@@ -228,11 +254,11 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
           return pass_ns(S2) - pass_ns(S) <= alpha * pass_ns(qh);
         },
         cand);
-    consider(cand);
+    consider(cand, 0);
   }
   for (auto& t : pool) t.join();
   if (!errs.empty()) std::rethrow_exception(errs.front());
-  for (auto& b : blk) consider(b);  // largest-block partitions, in the order they were started
+  for (auto& b : blk) consider(b.blocks, b.ctrl);  // largest-block partitions, in the order they were started
   // The phase-block partition: each run of phase gates is one elementwise
   // sweep, priced as a one-qubit pass on the top qubit (same traffic, no gather).
   double t_ph = 0;
@@ -272,8 +298,11 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
     block_of = std::move(ph_of);
     return true;
   }
-  if (keep_fewest) best.swap(fewest);
-  fuse_blocks(g, n, best, out, block_of);
+  if (keep_fewest) {
+    best.swap(fewest);
+    best_ctrl = fewest_ctrl;
+  }
+  fuse_blocks(g, n, best, out, block_of, best_ctrl);
   return true;
 }
 

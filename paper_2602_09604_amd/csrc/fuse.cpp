@@ -195,6 +195,122 @@ static void build_block(const sv_gate* g, const std::vector<int>& members, Fused
   }
 }
 
+bool is_diagonal_gate(const sv_gate& g) {
+  if (g.cmask) return false;
+  const int d = 1 << g.k;
+  for (int r = 0; r < d; ++r)
+    for (int c = 0; c < d; ++c)
+      if (r != c && (g.matrix[2 * (r * d + c)] != 0.0 || g.matrix[2 * (r * d + c) + 1] != 0.0)) return false;
+  return true;
+}
+
+void block_split(const sv_gate* g, const std::vector<int>& members, int max_ctrl, uint64_t& targets,
+                 uint64_t& controls) {
+  uint64_t all = 0, dense = 0;
+  for (int i : members) {
+    all |= qmask(g[i]);
+    if (max_ctrl > 0 && !is_diagonal_gate(g[i])) dense |= qmask(g[i]);
+  }
+  controls = 0;
+  if (max_ctrl > 0 && !(members.size() == 1 && g[members[0]].cmask)) {
+    uint64_t cand = all & ~dense & ~kCtrlLowBits;
+    for (int b = 63; b >= 0 && __builtin_popcountll(controls) < max_ctrl; --b)
+      if ((cand >> b) & 1) controls |= (uint64_t)1 << b;
+    if (controls == all) controls &= controls - 1;  // keep the lowest as the target
+  }
+  targets = all & ~controls;
+}
+
+// The fused gates of one block: one dense gate, or with controls one gate per
+// control value v, each the ordered product of the members with every
+// diagonal member that reaches a control restricted to the control bits of v
+// (a diagonal gate on its target part, or a phase when it has none there).
+static void build_block_mux(const sv_gate* g, const std::vector<int>& members, int max_ctrl,
+                            std::vector<FusedGate>& outs) {
+  uint64_t S = 0, Cm = 0;
+  block_split(g, members, max_ctrl, S, Cm);
+  outs.clear();
+  if (Cm == 0) {
+    outs.emplace_back();
+    build_block(g, members, outs.back());
+    return;
+  }
+  int K = 0, bitpos[64], cbits[64], nc = 0;
+  int q[SV_MAX_K];
+  for (int b = 0; b < 64; ++b) {
+    if ((S >> b) & 1) {
+      bitpos[b] = K;
+      q[K++] = b;
+    }
+    if ((Cm >> b) & 1) cbits[nc++] = b;
+  }
+  const int d = 1 << K;
+  std::vector<double> Mr, Mi, dmat;
+  for (int v = 0; v < (1 << nc); ++v) {
+    uint64_t cval = 0;
+    for (int t = 0; t < nc; ++t)
+      if ((v >> t) & 1) cval |= (uint64_t)1 << cbits[t];
+    Mr.assign((size_t)d * d, 0.0);
+    Mi.assign((size_t)d * d, 0.0);
+    for (int i = 0; i < d; ++i) Mr[(size_t)i * d + i] = 1.0;
+    for (int i : members) {
+      const sv_gate& h = g[i];
+      int pos[SV_MAX_K];
+      if ((qmask(h) & Cm) == 0) {
+        for (int j = 0; j < h.k; ++j) pos[j] = bitpos[h.qubits[j]];
+        left_multiply(Mr, Mi, K, h, pos);
+        continue;
+      }
+      // diagonal member reaching controls: its entries with the control bits fixed
+      const int dk = 1 << h.k;
+      int tj[SV_MAX_K], nt = 0, fixed = 0;
+      for (int j = 0; j < h.k; ++j) {
+        const int b = h.qubits[j];
+        if ((Cm >> b) & 1) {
+          if ((cval >> b) & 1) fixed |= 1 << j;
+        } else {
+          tj[nt] = j;
+          pos[nt++] = bitpos[b];
+        }
+      }
+      const int dr = 1 << nt;
+      dmat.assign((size_t)2 * dr * dr, 0.0);
+      for (int r = 0; r < dr; ++r) {
+        int l = fixed;
+        for (int t = 0; t < nt; ++t)
+          if ((r >> t) & 1) l |= 1 << tj[t];
+        dmat[2 * ((size_t)r * dr + r)] = h.matrix[2 * ((size_t)l * dk + l)];
+        dmat[2 * ((size_t)r * dr + r) + 1] = h.matrix[2 * ((size_t)l * dk + l) + 1];
+      }
+      if (nt == 0) {  // a phase for this control value
+        const double pr = dmat[0], pi = dmat[1];
+        for (size_t e = 0; e < (size_t)d * d; ++e) {
+          const double xr = Mr[e], xi = Mi[e];
+          Mr[e] = pr * xr - pi * xi;
+          Mi[e] = pr * xi + pi * xr;
+        }
+        continue;
+      }
+      sv_gate rg{};
+      rg.k = nt;
+      for (int t = 0; t < nt; ++t) rg.qubits[t] = h.qubits[tj[t]];
+      rg.matrix = dmat.data();
+      left_multiply(Mr, Mi, K, rg, pos);
+    }
+    FusedGate f;
+    f.k = K;
+    std::copy(q, q + K, f.q);
+    f.mat.resize((size_t)2 * d * d);
+    for (size_t e = 0; e < (size_t)d * d; ++e) {
+      f.mat[2 * e] = Mr[e];
+      f.mat[2 * e + 1] = Mi[e];
+    }
+    f.cmask = Cm;
+    f.cval = cval;
+    outs.push_back(std::move(f));
+  }
+}
+
 void fuse_none(const sv_gate* g, size_t n, std::vector<FusedGate>& out, std::vector<int32_t>& block_of) {
   out.clear();
   out.reserve(n);
@@ -272,22 +388,32 @@ namespace {
 struct BlockSearch {
   const sv_gate* g;
   std::vector<uint64_t> masks;
-  std::vector<int> live;  // indices of gates not yet emitted, in order
+  std::vector<char> diag;  // diagonal gates (candidates for control absorption)
+  std::vector<int> live;   // indices of gates not yet emitted, in order
 
   // Gates absorbed by S (indices into g, in order); optionally the candidate
   // qubit additions seen before S is fully blocked.
   bool narrow = false;  // additions only from gates whose qubits in S are not yet blocked
+  // With max_ctrl > 0 a diagonal gate that touches S may also reach up to
+  // max_ctrl qubits outside S (at or above kCtrlMinBit): those become control
+  // bits of the pass, which then applies one matrix per control value.
+  int max_ctrl = 0;
 
   int absorb(uint64_t S, std::vector<int>* got, std::vector<uint64_t>* adds) const {
-    uint64_t blocked = 0;
+    uint64_t blocked = 0, ctrl = 0;
     int count = 0;
     for (int h : live) {
       const uint64_t qh = masks[h];
       if ((S & ~blocked) == 0) break;  // every qubit of S is blocked: nothing more can join
-      if ((qh & blocked) == 0 && (qh & ~S) == 0 && !g[h].cmask) {
-        ++count;
-        if (got) got->push_back(h);
-        continue;
+      if ((qh & blocked) == 0 && !g[h].cmask) {
+        const uint64_t out = qh & ~S;
+        if (out == 0 || (max_ctrl > 0 && diag[h] && (qh & S) && (out & kCtrlLowBits) == 0 &&
+                         __builtin_popcountll(ctrl | out) <= max_ctrl)) {
+          ctrl |= out;
+          ++count;
+          if (got) got->push_back(h);
+          continue;
+        }
       }
       if (adds && !g[h].cmask && (qh & S & (narrow ? ~blocked : ~(uint64_t)0)) && (qh & ~S)) adds->push_back(qh & ~S);
       blocked |= qh;
@@ -350,21 +476,25 @@ std::pair<int, uint64_t> grow_from(const BlockSearch& b, const std::vector<int>&
   return {seen, seen_S};
 }
 
-void init_search(BlockSearch& b, const sv_gate* g, size_t n) {
+void init_search(BlockSearch& b, const sv_gate* g, size_t n, int max_ctrl) {
   b.g = g;
+  b.max_ctrl = max_ctrl;
   b.masks.resize(n);
+  b.diag.assign(n, 0);
   b.live.clear();
   for (size_t i = 0; i < n; ++i) {
     b.masks[i] = qmask(g[i]);
+    if (max_ctrl > 0) b.diag[i] = is_diagonal_gate(g[i]);
     b.live.push_back((int)i);
   }
 }
 }  // namespace
 
-void maxblock_partition(const sv_gate* g, size_t n, int max_k, bool narrow, std::vector<std::vector<int>>& blocks) {
+void maxblock_partition(const sv_gate* g, size_t n, int max_k, bool narrow, std::vector<std::vector<int>>& blocks,
+                        int max_ctrl) {
   blocks.clear();
   BlockSearch b;
-  init_search(b, g, n);
+  init_search(b, g, n, max_ctrl);
   b.narrow = narrow;
   std::vector<char> done(n, 0);
   std::vector<uint64_t> adds;
@@ -536,13 +666,13 @@ class RoundPool {
 }  // namespace
 
 void beam_partition(const sv_gate* g, size_t n, int max_k, int width, int topm,
-                    std::vector<std::vector<int>>& blocks) {
+                    std::vector<std::vector<int>>& blocks, int max_ctrl) {
   blocks.clear();
   if (n == 0) return;
   width = std::max(width, 1);
   topm = std::max(topm, 1);
   BlockSearch proto;
-  init_search(proto, g, n);
+  init_search(proto, g, n, max_ctrl);
   std::vector<BeamNode> beam(1);
   beam[0].live = proto.live;
   const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -612,44 +742,49 @@ void fuse_maxblock(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>
 }
 
 void fuse_blocks(const sv_gate* g, size_t n, const std::vector<std::vector<int>>& blocks,
-                 std::vector<FusedGate>& out, std::vector<int32_t>& block_of) {
+                 std::vector<FusedGate>& out, std::vector<int32_t>& block_of, int max_ctrl) {
   out.clear();
-  out.resize(blocks.size());
   block_of.assign(n, -1);
-  for (size_t b = 0; b < blocks.size(); ++b)
-    for (int i : blocks[b]) block_of[i] = (int32_t)b;
   // The block matrices are independent: build them on host threads when
   // there is enough work to pay for the threads (many large blocks), and
   // never from inside another pool's worker.
   const size_t nb = blocks.size();
+  std::vector<std::vector<FusedGate>> built(nb);
   size_t work = 0;  // gate products times block dimension squared
   for (size_t b = 0; b < nb; ++b) {
     uint64_t S = 0;
     for (int i : blocks[b]) S |= qmask(g[i]);
-    work += blocks[b].size() << (2 * __builtin_popcountll(S));
+    work += blocks[b].size() << (2 * std::min(__builtin_popcountll(S), SV_MAX_K));
   }
   const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   const unsigned nt = host_pool_worker() || work < ((size_t)1 << 20) ? 1u : (unsigned)std::min<size_t>(hw, nb / 4);
   if (nt <= 1) {
-    for (size_t b = 0; b < nb; ++b) build_block(g, blocks[b], out[b]);
-    return;
+    for (size_t b = 0; b < nb; ++b) build_block_mux(g, blocks[b], max_ctrl, built[b]);
+  } else {
+    std::atomic<size_t> next{0};
+    std::vector<std::exception_ptr> errs(nt);
+    auto worker = [&](unsigned w) {
+      try {
+        for (size_t b = next++; b < nb; b = next++) build_block_mux(g, blocks[b], max_ctrl, built[b]);
+      } catch (...) {  // carried back to the caller; an exception must not end a thread
+        errs[w] = std::current_exception();
+        next = nb;
+      }
+    };
+    std::vector<std::thread> pool;
+    for (unsigned w = 1; w < nt; ++w) pool.emplace_back(worker, w);
+    worker(0);
+    for (auto& t : pool) t.join();
+    for (auto& e : errs)
+      if (e) std::rethrow_exception(e);
   }
-  std::atomic<size_t> next{0};
-  std::vector<std::exception_ptr> errs(nt);
-  auto worker = [&](unsigned w) {
-    try {
-      for (size_t b = next++; b < nb; b = next++) build_block(g, blocks[b], out[b]);
-    } catch (...) {  // carried back to the caller; an exception must not end a thread
-      errs[w] = std::current_exception();
-      next = nb;
-    }
-  };
-  std::vector<std::thread> pool;
-  for (unsigned w = 1; w < nt; ++w) pool.emplace_back(worker, w);
-  worker(0);
-  for (auto& t : pool) t.join();
-  for (auto& e : errs)
-    if (e) std::rethrow_exception(e);
+  size_t total = 0;
+  for (auto& v : built) total += v.size();
+  out.reserve(total);
+  for (size_t b = 0; b < nb; ++b) {
+    for (int i : blocks[b]) block_of[i] = (int32_t)out.size();
+    for (auto& f : built[b]) out.push_back(std::move(f));
+  }
 }
 
 void fuse_greedy(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>& out,

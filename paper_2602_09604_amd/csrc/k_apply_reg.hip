@@ -113,14 +113,14 @@ void launch_lds(const Pass& p, int n, void* psi, const float2* U, hipStream_t st
 // distinct, < n; k <= n; LDS tile fits); this only dispatches.
 void launch_pass(const Pass& p, int n, void* psi, const unsigned char* arena_dev, hipStream_t st) {
   const unsigned char* data = arena_dev + p.mat_off;
-  if (p.cmask) {
+  if (p.variant == V_MFMA) {  // with or without controls
+    launch_mfma(p, n, psi, data, st);
+  } else if (p.cmask) {
     launch_ctrl(p, n, psi, reinterpret_cast<const float2*>(data), st);
   } else if (p.variant == V_SHFL) {
     launch_shfl(p, n, psi, reinterpret_cast<const float2*>(data), st);
   } else if (p.variant == V_PHASE) {
     launch_phase(n, psi, data, p.nhubs, p.hub, st);
-  } else if (p.variant == V_MFMA) {
-    launch_mfma(p, n, psi, data, st);
   } else if (p.variant == V_LDS) {
     launch_lds(p, n, psi, reinterpret_cast<const float2*>(data), st);
   } else {

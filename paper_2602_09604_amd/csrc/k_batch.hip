@@ -178,7 +178,7 @@ void set_batch_lds_max_n(int n) {
 }
 
 int plan_fusion(const sv_gate* g, size_t n, int n_qubits, const sv_run_opts& o, std::vector<FusedGate>& fused,
-                std::vector<int32_t>& block_of);
+                std::vector<int32_t>& block_of, int max_ctrl);
 
 // Batched run on explicit buffers; lds_max_n < 0 uses the tuned limit.
 void batch_run_impl(void* const* psis, const int* ns, const sv_gate* const* circuits, const size_t* n_gates,
@@ -206,7 +206,7 @@ void batch_run_impl(void* const* psis, const int* ns, const sv_gate* const* circ
       try {
         for (size_t c = next++; c < n_circ; c = next++) {
           std::vector<int32_t> block_of;
-          plan_fusion(circuits[c], n_gates[c], ns[c], o, plans[c], block_of);
+          plan_fusion(circuits[c], n_gates[c], ns[c], o, plans[c], block_of, 0);  // batched passes take no controls
         }
       } catch (...) {
         errs[w] = std::current_exception();

@@ -20,6 +20,7 @@
 //              normalised state, |c| <= 1, stays below the fp16 maximum and
 //              amplitudes down to ~4e-9 stay normal); two FP32 accumulators
 //              (hi*hi and the 2^11-scaled cross terms) combined at the end.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <type_traits>
@@ -63,18 +64,24 @@ __device__ __forceinline__ short dev_bf16(float f) {
 }
 __device__ __forceinline__ float dev_bf16_f(short h) { return __uint_as_float((uint32_t)(uint16_t)h << 16); }
 
+// Controls of a controlled pass: the pass covers only the groups whose
+// control bits equal cval; at most kMfmaCtrl of them.
+constexpr int kMfmaCtrl = 3;
+
 struct MfmaArgs {
-  uint64_t tiles;                // 32-column tiles
-  uint64_t lowmask64[SV_MAX_K];  // element-space insertion masks, ascending
-  uint64_t stride[SV_MAX_K];     // element stride of local bit j (element = float4)
-  int kq;                        // number of element-space targets
+  uint64_t tiles;                          // 32-column tiles
+  uint64_t ins[SV_MAX_K + kMfmaCtrl];      // element-space zero-insertion masks of the targets
+                                           // and controls, ascending; ~0 (a no-op) in unused slots
+  uint64_t cbits;                          // element-space control values, ORed into every base
+  uint64_t stride[SV_MAX_K];               // element stride of local bit j (element = float4)
+  int kq;                                  // number of element-space targets
 };
 
 template <int KQ>
 __device__ __forceinline__ uint64_t mf_base(uint64_t g, const MfmaArgs& a) {
 #pragma unroll
-  for (int j = 0; j < KQ; ++j) g = ((g & ~a.lowmask64[j]) << 1) | (g & a.lowmask64[j]);
-  return g;
+  for (int j = 0; j < KQ + kMfmaCtrl; ++j) g = ((g & ~a.ins[j]) << 1) | (g & a.ins[j]);
+  return g | a.cbits;
 }
 
 template <int KQ>
@@ -350,28 +357,46 @@ void mfma_encode(const Pass& p, const double* mat, unsigned char* dst) {
         }
 }
 
+bool mfma_ctrl_supported(int n, int k, uint64_t cmask) {
+  const int c = __builtin_popcountll(cmask);
+  return c <= kMfmaCtrl && (cmask & 1) == 0 && n - 1 - k - c >= 5;
+}
+
 void launch_mfma(const Pass& p, int n, void* psi, const unsigned char* data, hipStream_t st) {
+  if (p.cmask && !mfma_ctrl_supported(n, p.k, p.cmask))
+    throw DeviceError{hipErrorInvalidValue, "k_apply_mfma: unsupported controls"};
   MfmaArgs a{};
   int pos[SV_MAX_K];
   int layout;
+  const int c = __builtin_popcountll(p.cmask);
   if (p.s[0] == 0) {
     layout = kLayoutQ0;
     a.kq = p.k - 1;
     for (int j = 0; j < a.kq; ++j) pos[j] = p.s[j + 1] - 1;
-    a.tiles = ((uint64_t)1 << (n - p.k)) / 32;
+    a.tiles = ((uint64_t)1 << (n - p.k - c)) / 32;
   } else {
     layout = kLayoutPair;
     a.kq = p.k;
     for (int j = 0; j < a.kq; ++j) pos[j] = p.s[j] - 1;
-    a.tiles = ((uint64_t)1 << (n - 1 - p.k)) / 32;
+    a.tiles = ((uint64_t)1 << (n - 1 - p.k - c)) / 32;
   }
-  for (int j = 0; j < a.kq; ++j) {
-    a.lowmask64[j] = ((uint64_t)1 << pos[j]) - 1;
-    a.stride[j] = (uint64_t)1 << pos[j];
-  }
+  for (int j = 0; j < a.kq; ++j) a.stride[j] = (uint64_t)1 << pos[j];
+  // zero insertion at targets and controls together, in ascending position;
+  // amplitude bit b >= 1 is element bit b - 1 (an element holds bits 0 free)
+  int ins[SV_MAX_K + kMfmaCtrl], m = 0;
+  for (int j = 0; j < a.kq; ++j) ins[m++] = pos[j];
+  for (int b = 1; b < 64; ++b)
+    if ((p.cmask >> b) & 1) {
+      ins[m++] = b - 1;
+      if ((p.cval >> b) & 1) a.cbits |= (uint64_t)1 << (b - 1);
+    }
+  std::sort(ins, ins + m);
+  for (int j = 0; j < SV_MAX_K + kMfmaCtrl; ++j) a.ins[j] = j < m ? ((uint64_t)1 << ins[j]) - 1 : ~(uint64_t)0;
   if (a.tiles == 0) throw DeviceError{hipErrorInvalidValue, "k_apply_mfma: state too small for a 32-group tile"};
   const bool pair = layout == kLayoutPair;
-  const bool nt = kern::gather_nt(n, p.k, p.s);
+  // streaming stores only when no target or control leaves partial lines
+  bool nt = kern::gather_nt(n, p.k, p.s);
+  if (p.cmask & 0xEull) nt = false;
   switch (p.precision) {
     case SV_PREC_FP32_MFMA:
       pair ? launch_k<SV_PREC_FP32_MFMA, kLayoutPair>(p.k, nt, a, psi, data, st)

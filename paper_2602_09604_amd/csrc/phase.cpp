@@ -20,8 +20,6 @@
 
 namespace sv {
 
-void fuse_blocks(const sv_gate* g, size_t n, const std::vector<std::vector<int>>& blocks,
-                 std::vector<FusedGate>& out, std::vector<int32_t>& block_of);
 
 namespace {
 constexpr double kTwoPi = 6.283185307179586476925286766559;

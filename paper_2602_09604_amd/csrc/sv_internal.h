@@ -90,6 +90,9 @@ int norm_partials_needed();
 size_t pass_data_bytes(const Pass& p);
 void encode_pass_data(const Pass& p, const double* mat, unsigned char* dst);
 bool mfma_supported(int k, int precision);
+// Controls the matrix-core kernel takes: at most three, none on bit 0, and at
+// least one 32-group tile left.
+bool mfma_ctrl_supported(int n, int k, uint64_t cmask);
 
 // Planning helpers (plan.cpp).
 void normalise_gate(int k, const int32_t* qubits, const double* mat, int* sorted_out,
@@ -123,11 +126,33 @@ void fuse_greedy(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>& 
 void fuse_none(const sv_gate* g, size_t n, std::vector<FusedGate>& out, std::vector<int32_t>& block_of);
 void fuse_maxblock(const sv_gate* g, size_t n, int max_k, std::vector<FusedGate>& out,
                    std::vector<int32_t>& block_of);
-void maxblock_partition(const sv_gate* g, size_t n, int max_k, bool narrow, std::vector<std::vector<int>>& blocks);
+// Partition searches.  max_ctrl > 0 lets a block take diagonal gates that
+// reach outside its qubits as controls (see block_split).
+void maxblock_partition(const sv_gate* g, size_t n, int max_k, bool narrow, std::vector<std::vector<int>>& blocks,
+                        int max_ctrl = 0);
 void beam_partition(const sv_gate* g, size_t n, int max_k, int width, int topm,
-                    std::vector<std::vector<int>>& blocks);
+                    std::vector<std::vector<int>>& blocks, int max_ctrl = 0);
+// Fused gates of a partition, in block order; block_of[i] is the index of
+// the first fused gate of gate i's block.  With max_ctrl > 0 a block may come
+// out as 2^c controlled gates on the same targets, one per control value.
 void fuse_blocks(const sv_gate* g, size_t n, const std::vector<std::vector<int>>& blocks,
-                 std::vector<FusedGate>& out, std::vector<int32_t>& block_of);
+                 std::vector<FusedGate>& out, std::vector<int32_t>& block_of, int max_ctrl = 0);
+// Control bits a block may use: at or above kCtrlMinBit, so that every
+// control value covers runs of at least 2^7 amplitudes (1 KiB).
+constexpr int kCtrlMinBit = 7;
+constexpr uint64_t kCtrlLowBits = ((uint64_t)1 << kCtrlMinBit) - 1;
+// Controls a fused block takes when the search allows them, and the smallest
+// state where it does: a block with c controls runs as 2^c launches, each
+// over 2^-c of the state, which must still fill the GPU.
+constexpr int kBlockCtrl = 3;
+constexpr int kBlockCtrlMinQubits = 28;
+bool is_diagonal_gate(const sv_gate& g);
+// Targets and controls of a block: every qubit that only diagonal members
+// touch, at or above kCtrlMinBit, may be a control (the block's unitary is
+// block-diagonal in it); the highest such qubits become controls, at most
+// max_ctrl of them, and at least one qubit stays a target.
+void block_split(const sv_gate* g, const std::vector<int>& members, int max_ctrl, uint64_t& targets,
+                 uint64_t& controls);
 // Set on threads of a host worker pool so that the work they call does not
 // start threads of its own.
 bool host_pool_worker();
@@ -172,8 +197,9 @@ void launch_marginal(const void* psi, int n, int m, const int* qubits, double* s
 size_t sample_scratch_bytes(int n);
 void launch_sample(const void* psi, int n, bool prepare, const double* uniforms, uint64_t shots, uint64_t* out,
                    double* scratch, hipStream_t st);
+// Learned fusion; max_ctrl > 0 adds candidates whose blocks take controls.
 bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int precision,
-                  std::vector<FusedGate>& out, std::vector<int32_t>& block_of);
+                  std::vector<FusedGate>& out, std::vector<int32_t>& block_of, int max_ctrl);
 
 // Cost model (cost_model.cpp).
 void cost_features(int k, const int* qubits, int n, int precision, float* out);

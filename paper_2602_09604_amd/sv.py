@@ -51,12 +51,13 @@ class sv_run_stats(ctypes.Structure):
     _fields_ = [("gates_in", ctypes.c_uint64), ("passes", ctypes.c_uint64), ("bytes", ctypes.c_uint64),
                 ("useful_flops", ctypes.c_double), ("fuse_s", ctypes.c_double), ("gpu_s", ctypes.c_double),
                 ("variant_s", ctypes.c_double * 5), ("variant_passes", ctypes.c_uint64 * 5),
-                ("graph_relaunched", ctypes.c_uint64)]
+                ("graph_relaunched", ctypes.c_uint64), ("variant_bytes", ctypes.c_uint64 * 5)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
         d["variant_s"] = list(self.variant_s)
         d["variant_passes"] = list(self.variant_passes)
+        d["variant_bytes"] = list(self.variant_bytes)
         return d
 
 

@@ -9,6 +9,7 @@ import pytest
 
 import circuits as C
 import oracle
+from partition_check import check_partition, sweeps
 from paper_2602_09604_amd import sv
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -42,17 +43,7 @@ def test_version_and_last_error():
 # Fusion (host FP64), checked against the unfused oracle
 # --------------------------------------------------------------------------
 def _check_partition(gates, fused, block_of, max_k):
-    assert len(block_of) == len(gates)
-    assert set(block_of.tolist()) == set(range(len(fused)))
-    for f in fused:
-        assert 1 <= f.k <= max_k
-        assert list(f.qubits) == sorted(f.qubits)
-    for i, g in enumerate(gates):  # every gate's qubits are inside its block
-        assert set(g.qubits) <= set(fused[block_of[i]].qubits)
-    n = max(q for g in gates for q in g.qubits) + 1
-    for q in range(n):  # per-qubit program order is preserved
-        seq = [int(block_of[i]) for i, g in enumerate(gates) if q in g.qubits]
-        assert seq == sorted(seq)
+    return check_partition(gates, fused, block_of, max_k)
 
 
 @needs_lib
@@ -230,7 +221,7 @@ def test_learned_without_model_keeps_fewest_passes():
     from paper_2602_09604_amd import costmodel  # noqa: F401  (no model is installed in the CPU suite)
     gates = C.grid_circuit(3, 4, 12, seed=2)
     n = 12
-    counts = {f: len(sv.sv_fuse(gates, n, sv.make_opts(max_k=5, fusion=f))[0]) for f in ("greedy", "block", "learned")}
+    counts = {f: sweeps(sv.sv_fuse(gates, n, sv.make_opts(max_k=5, fusion=f))[1]) for f in ("greedy", "block", "learned")}
     assert counts["learned"] <= min(counts["greedy"], counts["block"]), counts
     fused, _ = sv.sv_fuse(gates, n, sv.make_opts(max_k=5, fusion="learned"))
     ref = oracle.apply_circuit(n, gates)
@@ -240,8 +231,8 @@ def test_learned_without_model_keeps_fewest_passes():
 @needs_lib
 @pytest.mark.parametrize("case", ["random8_k5", "random12_k3", "grid4x3_k6"])
 def test_beam_search_finds_fewer_passes(case):
-    """Learned fusion without a model includes a beam search over
-    largest-block passes; on these circuits it needs one pass fewer than the
+    """Learned fusion without a model includes beam searches over
+    largest-block passes; on these circuits it needs fewer passes than the
     largest-block rule, and its partition reaches the unfused state."""
     from paper_2602_09604_amd import costmodel  # noqa: F401  (no model is installed in the CPU suite)
     n, max_k, gates = {
@@ -253,21 +244,66 @@ def test_beam_search_finds_fewer_passes(case):
     block, _ = sv.sv_fuse(gates, n, sv.make_opts(max_k=max_k, fusion="block"))
     fused, block_of = sv.sv_fuse(gates, n, sv.make_opts(max_k=max_k, fusion="learned"))
     _check_partition(gates, fused, block_of, max_k)
-    assert len(fused) < len(block), (len(fused), len(block))
+    assert sweeps(block_of) < len(block), (sweeps(block_of), len(block))
     ref = oracle.apply_circuit(n, gates, init=3)
     assert np.max(np.abs(oracle.apply_circuit(n, fused, init=3) - ref)) < 1e-12
 
 
 @needs_lib
-def test_beam_search_on_34_qubit_grid():
-    """The 2x17 depth-24 grid: the beam search takes it from 53 largest-block
-    passes to at most 50, with a valid partition."""
+def test_learned_fusion_on_34_qubit_grid():
+    """The 2x17 depth-24 grid: 53 largest-block passes; the beam search alone
+    reaches 49 and blocks with controls (CZs to outside qubits taken as
+    control bits) at most 35 sweeps, with a valid partition."""
     gates = C.grid_circuit(2, 17, 24, seed=0)
     fused, block_of = sv.sv_fuse(gates, 34, sv.make_opts(max_k=6, fusion="learned"))
-    _check_partition(gates, fused, block_of, 6)
-    assert len(fused) <= 50, len(fused)
+    assert check_partition(gates, fused, block_of, 6) <= 35
+    ctrl = [f for f in fused if f.controls]
+    assert ctrl and all(min(f.controls) >= 7 and len(f.controls) <= 3 for f in ctrl)
 
 
+@needs_lib
+@pytest.mark.parametrize("rows,cols,depth,max_k,seed", [(3, 4, 12, 4, 0), (2, 6, 16, 5, 1), (3, 4, 20, 6, 2),
+                                                         (4, 3, 14, 3, 3), (2, 5, 30, 6, 4)])
+def test_blocks_with_controls_equivalent(rows, cols, depth, max_k, seed):
+    """Blocks that take diagonal gates reaching outside qubits as controls
+    (one fused gate per control value) reach the unfused state through the
+    oracle; the grids are chosen so that such blocks occur.  The fusion is
+    planned for a 30-qubit state (blocks take controls from 28 qubits up) and
+    checked on the circuit's own qubits."""
+    n = rows * cols
+    gates = C.grid_circuit(rows, cols, depth, seed=seed)
+    fused, block_of = sv.sv_fuse(gates, 30, sv.make_opts(max_k=max_k, fusion="learned"))
+    check_partition(gates, fused, block_of, max_k)
+    assert any(f.controls for f in fused)
+    block, _ = sv.sv_fuse(gates, 30, sv.make_opts(max_k=max_k, fusion="block"))
+    assert sweeps(block_of) <= len(block)
+    small, small_of = sv.sv_fuse(gates, n, sv.make_opts(max_k=max_k, fusion="learned"))
+    assert not any(f.controls for f in small)  # below 28 qubits no block takes controls
+    ref = oracle.apply_circuit(n, gates, init=seed + 5)
+    assert np.max(np.abs(oracle.apply_circuit(n, fused, init=seed + 5) - ref)) < 1e-12
+
+
+@needs_lib
+def test_block_split_rules():
+    """Dense gates on (0, 1) interleaved with CZ(1, 9), CZ(0, 8) and CZ(0, 3),
+    max_k = 3: qubits 8 and 9 (at or above bit 7) become controls of one
+    block on (0, 1, 3); qubit 3 stays a target.  Then single-qubit gates on 8
+    and 9 form the second block."""
+    rng = np.random.Generator(np.random.PCG64(11))
+    u = lambda k: C.haar_unitary(k, rng)  # noqa: E731
+    gates = [C.Gate((0, 1), u(2)), C.Gate((1, 9), C.CZ), C.Gate((0, 1), u(2)), C.Gate((0, 8), C.CZ),
+             C.Gate((0, 3), C.CZ), C.Gate((0, 1), u(2)), C.Gate((9,), u(1)), C.Gate((8,), u(1))]
+    fused, block_of = sv.sv_fuse(gates, 30, sv.make_opts(max_k=3, fusion="learned"))
+    assert check_partition(gates, fused, block_of, 3) == 2
+    first = fused[0]
+    assert first.controls == (8, 9) and first.qubits == (0, 1, 3)
+    assert sorted(tuple(f.control_values) for f in fused[:4]) == [(0, 0), (0, 1), (1, 0), (1, 1)]
+    assert list(block_of[:6]) == [0] * 6 and block_of[6] == block_of[7] == 4
+    ref = oracle.apply_circuit(10, gates, init=77)
+    assert np.max(np.abs(oracle.apply_circuit(10, fused, init=77) - ref)) < 1e-12
+
+
+@needs_lib
 def test_struct_layouts_match_binding():
     """The ctypes mirrors of the ABI structs have the library's sizes."""
     from paper_2602_09604_amd import sv

@@ -142,6 +142,38 @@ def test_controlled_circuits_vs_oracle(fusion, prec, max_k):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["fp16x3", "bf16x3", "fp32_mfma"])
+@pytest.mark.parametrize("case", [
+    # (n, targets, controls, values): k >= 4 controlled passes on the matrix cores
+    (14, (2, 3, 5, 9), (12,), (1,)),
+    (16, (0, 4, 5, 6, 7), (1, 15), (0, 1)),          # bit-0 target layout; a control on bit 1
+    (18, (10, 11, 12, 13, 14, 15), (3, 7, 17), (1, 0, 1)),
+    (18, (1, 2, 8, 9, 16, 17), (4, 5, 6), None),
+    (13, (0, 1, 2, 3, 4, 5), (6,), (0,)),            # the smallest state with one tile left
+    (26, (9, 14, 20, 25), (7, 12), (1, 1)),          # streaming stores
+    (26, (0, 8, 16, 24, 25), (3, 22, 23), (0, 1, 0)),
+])
+def test_controlled_matrix_core_passes(case, prec):
+    """Controlled k = 4..6 passes run on the matrix-core kernel (controls as
+    extra fixed bits, the control values ORed into every group's base)."""
+    n, ts, cs, vals = case
+    rng = np.random.Generator(np.random.PCG64(7 * n + len(ts) + len(cs)))
+    gates = [C.Gate(ts, C.haar_unitary(len(ts), rng), cs, vals),
+             C.Gate(tuple(reversed(ts)), C.haar_unitary(len(ts), rng), cs, None)]
+    ref = oracle.apply_circuit(n, prep(n, 3) + gates)
+    st = sv.State(n)
+    try:
+        st.apply_circuit(prep(n, 3), fusion="none")
+        s = st.apply_circuit(gates, fusion="none", precision=prec, stats=True, timing=True)
+        assert s["variant_passes"][3] == 2, s  # both on the matrix-core kernel
+        assert s["bytes"] == 2 * (16 << (n - len(cs)))
+        r = oracle.compare(st.read(), ref)
+        assert r["max_abs"] <= 1e-5 and r["infidelity"] <= 1e-6, r
+    finally:
+        st.free()
+
+
+@pytest.mark.gpu
 def test_controlled_pass_bytes_counted():
     n = 20
     st = sv.State(n)

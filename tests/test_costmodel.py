@@ -8,6 +8,7 @@ import pytest
 
 import circuits as C
 import oracle
+from partition_check import check_partition
 from paper_2602_09604_amd import sv
 
 needs_lib = pytest.mark.skipif(not os.path.exists(sv.LIB_PATH), reason="libsv.so not built")
@@ -57,8 +58,7 @@ def test_learned_fusion_with_constant_model_is_valid(tmp_path):
     n = 10
     gates = C.grid_circuit(2, 5, 10, seed=3)
     fused, block_of = sv.sv_fuse(gates, n, sv.make_opts(max_k=5, fusion="learned"))
-    assert all(f.k <= 5 for f in fused)
-    assert sorted(set(block_of.tolist())) == list(range(len(fused)))
+    check_partition(gates, fused, block_of, 5)
     ref = oracle.apply_circuit(n, gates)
     assert np.max(np.abs(oracle.apply_circuit(n, fused) - ref)) < 1e-12
 

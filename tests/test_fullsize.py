@@ -106,13 +106,14 @@ def test_grid34_factorised_sampled(state34, prec, fusion):
     assert drift <= (3e-5 if prec == "bf16x3" else 1e-5), drift
 
 
-def test_grid34_mirror_returns_to_zero(state34):
+@pytest.mark.parametrize("fusion", ["greedy", "learned"])
+def test_grid34_mirror_returns_to_zero(state34, fusion):
     """C followed by C^dagger on the 34-qubit grid (12 cycles each way) must
-    return |0...0>."""
+    return |0...0> (learned fusion: blocks with controls included)."""
     gates = C.grid_circuit(ROWS, COLS, 12, seed=9)
     st = state34
     st.set_basis(0)
-    st.apply_circuit(C.mirror_circuit(gates), max_k=6, fusion="greedy", precision="fp16x3")
+    st.apply_circuit(C.mirror_circuit(gates), max_k=6, fusion=fusion, precision="fp16x3")
     p0 = abs(complex(st.read(0, 1)[0])) ** 2
     norm = st.norm()
     say("mirror |psi_0|^2 =", p0, "norm", norm)

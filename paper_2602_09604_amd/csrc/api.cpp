@@ -124,7 +124,7 @@ static std::vector<unsigned char> graph_key(const std::vector<Pass>& passes, con
   f.reserve(passes.size() * 28);
   for (const Pass& p : passes) {
     f.insert(f.end(), {p.k, p.variant, p.precision, (int64_t)p.mat_off, (int64_t)p.mat_bytes, p.tile_bits,
-                       p.reg_iters, p.mfma_cols, p.nhubs, (int64_t)p.cmask, (int64_t)p.cval});
+                       p.reg_iters, p.mfma_cols, p.nhubs, (int64_t)p.cmask, (int64_t)p.cval, p.nmux});
     f.insert(f.end(), p.s, p.s + SV_MAX_K);
     f.insert(f.end(), p.hub, p.hub + 8);
   }
@@ -136,11 +136,12 @@ static std::vector<unsigned char> graph_key(const std::vector<Pass>& passes, con
 
 // Flops and algorithmic bytes of one pass; a controlled pass with c controls
 // works on 2^(n-k-c) groups and moves 16 * 2^(n-c) bytes.
+static int covered_ctrl_bits(const Pass& p) { return p.nmux > 1 ? 0 : __builtin_popcountll(p.cmask); }
 static double useful_flops(int n, const Pass& p) {
-  const int c = __builtin_popcountll(p.cmask);
+  const int c = covered_ctrl_bits(p);
   return std::ldexp(1.0, n - p.k - c) * (double)(1 << p.k) * (8.0 * (1 << p.k) - 2.0);
 }
-static uint64_t pass_bytes(int n, const Pass& p) { return (uint64_t)16 << (n - __builtin_popcountll(p.cmask)); }
+static uint64_t pass_bytes(int n, const Pass& p) { return (uint64_t)16 << (n - covered_ctrl_bits(p)); }
 
 // Resolve variants, encode all pass data into one staging region, copy it
 // with one host-to-device transfer, and launch the passes (optionally as one
@@ -152,6 +153,7 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
   // one pass holds); everything else is a matrix pass.
   std::vector<Pass> passes;
   std::vector<const double*> mats;               // matrix passes: the fused matrix
+  std::vector<std::vector<const double*>> mux;   // multiplexed passes: the matrix of each control value
   std::vector<std::vector<float>> phase_data;    // phase passes: their tables
   size_t total = 0;
   auto add = [&](Pass& p) {
@@ -177,6 +179,7 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
         p.mat_bytes = sizeof(float) * t.tab.size();
         add(p);
         mats.push_back(nullptr);
+        mux.emplace_back();
         phase_data.push_back(std::move(t.tab));
       }
       i = j;
@@ -189,8 +192,40 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
     p.cmask = fused[i].cmask;
     p.cval = fused[i].cval;
     if (p.cmask) {  // controlled passes: matrix cores when they take the controls, else registers in FP32
-      if (mfma_supported(p.k, o.precision) && mfma_ctrl_supported(s->n, p.k, p.cmask) &&
-          o.variant != SV_VARIANT_REG && o.variant != SV_VARIANT_LDS && o.variant != SV_VARIANT_SHFL) {
+      const bool mfma = mfma_supported(p.k, o.precision) && mfma_ctrl_supported(s->n, p.k, p.cmask) &&
+                        o.variant != SV_VARIANT_REG && o.variant != SV_VARIANT_LDS && o.variant != SV_VARIANT_SHFL;
+      // A block with controls comes as one gate per control value on the
+      // same targets: on the matrix cores all of them are one launch.
+      const int c = __builtin_popcountll(p.cmask);
+      size_t j = i;
+      std::vector<const double*> by_value;
+      if (mfma) {
+        int cbit[kBlockCtrl + 1], nc = 0;
+        for (int b = 0; b < 64 && nc <= kBlockCtrl; ++b)
+          if ((p.cmask >> b) & 1) cbit[nc++] = b;
+        by_value.assign((size_t)1 << c, nullptr);
+        while (j < fused.size() && j - i < by_value.size() && fused[j].cmask == p.cmask && fused[j].k == p.k &&
+               std::equal(fused[j].q, fused[j].q + p.k, fused[i].q)) {
+          int v = 0;
+          for (int t = 0; t < nc; ++t)
+            if ((fused[j].cval >> cbit[t]) & 1) v |= 1 << t;
+          if (by_value[v]) break;  // a repeated value starts another block
+          by_value[v] = fused[j].mat.data();
+          ++j;
+        }
+      }
+      if (mfma && c >= 1 && j - i == ((size_t)1 << c)) {
+        p.variant = V_MFMA;
+        p.nmux = 1 << c;
+        p.mat_bytes = pass_data_bytes(p);
+        add(p);
+        mats.push_back(nullptr);
+        mux.push_back(std::move(by_value));
+        phase_data.emplace_back();
+        i = j;
+        continue;
+      }
+      if (mfma) {
         p.variant = V_MFMA;
       } else {
         p.precision = SV_PREC_FP32_VALU;
@@ -199,6 +234,7 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
       p.mat_bytes = pass_data_bytes(p);
       add(p);
       mats.push_back(fused[i].mat.data());
+      mux.emplace_back();
       phase_data.emplace_back();
       ++i;
       continue;
@@ -211,6 +247,7 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
     p.mat_bytes = pass_data_bytes(p);
     add(p);
     mats.push_back(fused[i].mat.data());
+    mux.emplace_back();
     phase_data.emplace_back();
     ++i;
   }
@@ -218,8 +255,14 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
   const size_t base = arena_take(s, total);
   for (size_t i = 0; i < passes.size(); ++i) {
     unsigned char* dst = s->arena_host + base + passes[i].mat_off;
-    if (passes[i].variant == V_PHASE) std::memcpy(dst, phase_data[i].data(), passes[i].mat_bytes);
-    else encode_pass_data(passes[i], mats[i], dst);
+    if (passes[i].variant == V_PHASE) {
+      std::memcpy(dst, phase_data[i].data(), passes[i].mat_bytes);
+    } else if (passes[i].nmux > 1) {
+      const size_t each = passes[i].mat_bytes / passes[i].nmux;
+      for (int v = 0; v < passes[i].nmux; ++v) encode_pass_data(passes[i], mux[i][v], dst + v * each);
+    } else {
+      encode_pass_data(passes[i], mats[i], dst);
+    }
   }
   const bool timing = o.timing && stats;
   const bool graph = o.use_graph && !timing;

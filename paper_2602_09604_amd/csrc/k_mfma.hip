@@ -69,19 +69,22 @@ __device__ __forceinline__ float dev_bf16_f(short h) { return __uint_as_float((u
 constexpr int kMfmaCtrl = 3;
 
 struct MfmaArgs {
-  uint64_t tiles;                          // 32-column tiles
+  uint64_t tiles;                          // 32-column tiles per control value
   uint64_t ins[SV_MAX_K + kMfmaCtrl];      // element-space zero-insertion masks of the targets
                                            // and controls, ascending; ~0 (a no-op) in unused slots
-  uint64_t cbits;                          // element-space control values, ORed into every base
+  uint64_t cbits[1 << kMfmaCtrl];          // element-space control bits of control value v,
+                                           // ORed into every base of that value's groups
   uint64_t stride[SV_MAX_K];               // element stride of local bit j (element = float4)
   int kq;                                  // number of element-space targets
+  int vbits;                               // log2 of the control values this launch covers; the
+                                           // matrix of value v follows that of v - 1
 };
 
 template <int KQ>
-__device__ __forceinline__ uint64_t mf_base(uint64_t g, const MfmaArgs& a) {
+__device__ __forceinline__ uint64_t mf_base(uint64_t g, uint64_t cb, const MfmaArgs& a) {
 #pragma unroll
   for (int j = 0; j < KQ + kMfmaCtrl; ++j) g = ((g & ~a.ins[j]) << 1) | (g & a.ins[j]);
-  return g | a.cbits;
+  return g | cb;
 }
 
 template <int KQ>
@@ -115,12 +118,18 @@ __device__ __forceinline__ void mfma_body(float4* __restrict__ psi, const float4
   constexpr int KQ = LAYOUT == kLayoutPair ? K : K - 1;  // element-space targets
   constexpr int COLS = LAYOUT == kLayoutPair ? 2 : 1;    // column tiles per lane
   const int tid = threadIdx.x;
+  // workgroups are dealt round-robin to the control values; each loads the
+  // matrix of its value and walks that value's tiles
+  const unsigned v = blockIdx.x & ((1u << a.vbits) - 1);
+  const uint64_t wg = blockIdx.x >> a.vbits;
+  const uint64_t cb = a.cbits[v];
+  Ag += (size_t)v * (FRAG_BYTES / 16);
   for (int i = tid; i < FRAG_BYTES / 16; i += 256) lds4[i] = Ag[i];
   __syncthreads();
   const int lane = tid & 63, h = lane >> 5, j = lane & 31;
-  const uint64_t wstride = (uint64_t)gridDim.x * 4;
-  for (uint64_t wt = (uint64_t)blockIdx.x * 4 + (tid >> 6); wt < a.tiles; wt += wstride) {
-    const uint64_t base = mf_base<KQ>(wt * 32 + j, a);
+  const uint64_t wstride = (uint64_t)(gridDim.x >> a.vbits) * 4;
+  for (uint64_t wt = wg * 4 + (tid >> 6); wt < a.tiles; wt += wstride) {
+    const uint64_t base = mf_base<KQ>(wt * 32 + j, cb, a);
     if constexpr (!SPLIT) {
       // ---- FP32: k-step s is amplitude s; this lane supplies part h ----
       float b[COLS][KS];
@@ -286,8 +295,10 @@ void launch_t(const MfmaArgs& a, void* psi, const unsigned char* data, hipStream
   const size_t lds = frag_bytes(K, PREC);
   // 8192 workgroups (32 per CU, four times what can be resident at once):
   // measured faster than one resident round or than one tile per wave.
-  uint64_t blocks = (a.tiles + 3) / 4;
-  if (blocks > 8192) blocks = 8192;
+  // They are shared out evenly over the control values.
+  uint64_t per_value = (a.tiles + 3) / 4;
+  if (per_value > (8192u >> a.vbits)) per_value = 8192u >> a.vbits;
+  const uint64_t blocks = per_value << a.vbits;
   if constexpr (MfmaPolicy<PREC, LAYOUT>::rolled)
     hipLaunchKernelGGL((k_apply_mfma_rolled<K, PREC, LAYOUT, NT>), dim3((unsigned)blocks), dim3(256), lds, st,
                        (float4*)psi, (const float4*)data, a);
@@ -316,7 +327,7 @@ bool mfma_supported(int k, int precision) {
          (precision == SV_PREC_FP32_MFMA || precision == SV_PREC_BF16X3 || precision == SV_PREC_FP16X3);
 }
 
-size_t mfma_data_bytes(const Pass& p) { return frag_bytes(p.k, p.precision); }
+size_t mfma_data_bytes(const Pass& p) { return frag_bytes(p.k, p.precision) * (p.nmux > 1 ? p.nmux : 1); }
 
 // A' in fragment order.  FP32: [mt][s][lane] with lane (h, i) holding
 // A'[32 mt + i][2 s + h].  Split: [mt][s][part][lane][e] with lane (h, i)
@@ -383,14 +394,26 @@ void launch_mfma(const Pass& p, int n, void* psi, const unsigned char* data, hip
   for (int j = 0; j < a.kq; ++j) a.stride[j] = (uint64_t)1 << pos[j];
   // zero insertion at targets and controls together, in ascending position;
   // amplitude bit b >= 1 is element bit b - 1 (an element holds bits 0 free)
-  int ins[SV_MAX_K + kMfmaCtrl], m = 0;
+  // With nmux > 1 one launch covers every control value: value v sets the
+  // t-th control (ascending) to bit t of v; else the one value p.cval.
+  int ins[SV_MAX_K + kMfmaCtrl], m = 0, cpos[kMfmaCtrl], nc = 0;
   for (int j = 0; j < a.kq; ++j) ins[m++] = pos[j];
   for (int b = 1; b < 64; ++b)
     if ((p.cmask >> b) & 1) {
       ins[m++] = b - 1;
-      if ((p.cval >> b) & 1) a.cbits |= (uint64_t)1 << (b - 1);
+      cpos[nc++] = b - 1;
     }
   std::sort(ins, ins + m);
+  if (p.nmux > 1) {
+    if (p.nmux != (1 << nc)) throw DeviceError{hipErrorInvalidValue, "k_apply_mfma: control values"};
+    a.vbits = nc;
+    for (int v = 0; v < p.nmux; ++v)
+      for (int t = 0; t < nc; ++t)
+        if ((v >> t) & 1) a.cbits[v] |= (uint64_t)1 << cpos[t];
+  } else {
+    for (int t = 0; t < nc; ++t)
+      if ((p.cval >> (cpos[t] + 1)) & 1) a.cbits[0] |= (uint64_t)1 << cpos[t];
+  }
   for (int j = 0; j < SV_MAX_K + kMfmaCtrl; ++j) a.ins[j] = j < m ? ((uint64_t)1 << ins[j]) - 1 : ~(uint64_t)0;
   if (a.tiles == 0) throw DeviceError{hipErrorInvalidValue, "k_apply_mfma: state too small for a 32-group tile"};
   const bool pair = layout == kLayoutPair;

@@ -69,6 +69,10 @@ struct Pass {
   // controlled passes: act only where (index & cmask) == cval
   uint64_t cmask = 0;
   uint64_t cval = 0;
+  // nmux > 1 (matrix cores only): one launch applies 2^c matrices, one per
+  // value of the c control bits in cmask (value v: control t = bit t of v),
+  // their data one after another; cval is unused
+  int nmux = 0;
 };
 
 // Launch shape defaults / tuned values.

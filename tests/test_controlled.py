@@ -158,8 +158,8 @@ def test_controlled_matrix_core_passes(case, prec):
     extra fixed bits, the control values ORed into every group's base)."""
     n, ts, cs, vals = case
     rng = np.random.Generator(np.random.PCG64(7 * n + len(ts) + len(cs)))
-    gates = [C.Gate(ts, C.haar_unitary(len(ts), rng), cs, vals),
-             C.Gate(tuple(reversed(ts)), C.haar_unitary(len(ts), rng), cs, None)]
+    gates = [C.Gate(ts, C.haar_unitary(len(ts), rng), cs, vals),  # same control values: two launches
+             C.Gate(tuple(reversed(ts)), C.haar_unitary(len(ts), rng), cs, vals)]
     ref = oracle.apply_circuit(n, prep(n, 3) + gates)
     st = sv.State(n)
     try:
@@ -167,6 +167,44 @@ def test_controlled_matrix_core_passes(case, prec):
         s = st.apply_circuit(gates, fusion="none", precision=prec, stats=True, timing=True)
         assert s["variant_passes"][3] == 2, s  # both on the matrix-core kernel
         assert s["bytes"] == 2 * (16 << (n - len(cs)))
+        r = oracle.compare(st.read(), ref)
+        assert r["max_abs"] <= 1e-5 and r["infidelity"] <= 1e-6, r
+    finally:
+        st.free()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["fp16x3", "fp32_mfma"])
+@pytest.mark.parametrize("case", [
+    # (n, targets, controls, order of the control values given, values left out)
+    (16, (2, 3, 5, 9), (12,), (1, 0), ()),
+    (18, (0, 4, 5, 6, 7, 8), (9, 17), (0, 1, 2, 3), ()),
+    (18, (10, 11, 12, 13, 14, 15), (7, 8, 16), (5, 0, 7, 2, 1, 6, 3, 4), ()),
+    (26, (9, 14, 20, 25), (7, 12, 22), tuple(range(8)), ()),
+    (18, (1, 2, 3, 4), (7, 8), (0, 1, 2, 3), (2,)),   # one value missing: one launch per value
+])
+def test_multiplexed_matrix_core_pass(case, prec):
+    """One gate per control value on the same targets (what a fused block
+    with controls becomes) runs as one matrix-core launch over the whole
+    state; a group with a value missing runs value by value."""
+    n, ts, cs, order, missing = case
+    rng = np.random.Generator(np.random.PCG64(5 * n + len(cs)))
+    gates = []
+    for v in order:
+        if v in missing:
+            continue
+        vals = tuple((v >> t) & 1 for t in range(len(cs)))
+        gates.append(C.Gate(ts, C.haar_unitary(len(ts), rng), cs, vals))
+    ref = oracle.apply_circuit(n, prep(n, 4) + gates)
+    st = sv.State(n)
+    try:
+        st.apply_circuit(prep(n, 4), fusion="none")
+        s = st.apply_circuit(gates, fusion="none", precision=prec, stats=True, timing=True)
+        if missing:
+            assert s["passes"] == len(gates) and s["variant_passes"][3] == len(gates)
+        else:
+            assert s["passes"] == 1 and s["variant_passes"][3] == 1, s
+            assert s["bytes"] == 16 << n
         r = oracle.compare(st.read(), ref)
         assert r["max_abs"] <= 1e-5 and r["infidelity"] <= 1e-6, r
     finally:

@@ -229,13 +229,15 @@ def other_workloads() -> dict:
             log("qft32 %s: %d passes %.3f s" % (fusion, s["passes"], s["gpu_s"]))
         marked, iters = 0x2D2D2D2D, 3
         grover = C.grover_circuit(n, marked, iters)
-        st.set_basis(0)
-        s = st.apply_circuit(grover, max_k=6, fusion="greedy", precision="fp16x3", stats=True)
-        out["grover32"] = {"gates": len(grover), "iterations": iters, "passes": s["passes"], "gpu_s": s["gpu_s"],
-                           "gates_per_s_gpu": len(grover) / s["gpu_s"],
-                           "alg_hbm_frac": s["bytes"] / s["gpu_s"] / 1e9 / HBM_PEAK_GBPS,
-                           "marked_probability": abs(complex(st.read(marked, 1)[0])) ** 2}
-        log("grover32:", out["grover32"])
+        for fusion in ("greedy", "learned"):
+            st.set_basis(0)
+            s = st.apply_circuit(grover, max_k=6, fusion=fusion, precision="fp16x3", stats=True)
+            key = "grover32" if fusion == "greedy" else "grover32_learned"
+            out[key] = {"gates": len(grover), "iterations": iters, "passes": s["passes"], "gpu_s": s["gpu_s"],
+                        "gates_per_s_gpu": len(grover) / s["gpu_s"],
+                        "alg_hbm_frac": s["bytes"] / s["gpu_s"] / 1e9 / HBM_PEAK_GBPS,
+                        "marked_probability": abs(complex(st.read(marked, 1)[0])) ** 2}
+            log(key + ":", out[key])
         # the network against the fewest-passes rule where they differ: FP32
         # on the VALU kernels, whose k = 6 passes are compute-bound
         grid = C.grid_circuit(4, 8, 20, seed=0)
@@ -246,7 +248,7 @@ def other_workloads() -> dict:
                                                  "gates_per_s_gpu": len(grid) / s["gpu_s"]}
             log("grid32 fp32_valu %s:" % fusion, out["grid32_fp32_valu_" + fusion])
         qv = C.quantum_volume_circuit(n, n, seed=0)
-        for fusion in ("greedy", "block"):
+        for fusion in ("greedy", "block", "learned"):
             st.set_basis(0)
             s = st.apply_circuit(qv, max_k=6, fusion=fusion, precision="fp16x3", stats=True)
             out["qv32_" + fusion] = {"gates": len(qv), "depth": n, "passes": s["passes"], "gpu_s": s["gpu_s"],

@@ -376,6 +376,14 @@ static int check_opts(const sv_run_opts& o) {
 }
 
 // Fuse per opts into `fused`.
+// Controls a fused block may take: only where its per-value matrices run as
+// one matrix-core launch (a precision the matrix cores take) on a state of at
+// least kBlockCtrlMinQubits; elsewhere the per-value passes would be
+// separate FP32 register launches, slower than the sweeps they save.
+static int block_ctrl(int n_qubits, int precision) {
+  return n_qubits >= kBlockCtrlMinQubits && mfma_supported(4, precision) ? kBlockCtrl : 0;
+}
+
 int plan_fusion(const sv_gate* g_in, size_t n, int n_qubits, const sv_run_opts& o, std::vector<FusedGate>& fused,
                 std::vector<int32_t>& block_of, int max_ctrl) {
   // controlled gates narrow enough to fuse are lifted to dense gates first
@@ -583,7 +591,7 @@ int sv_apply_circuit(sv_state* s, const sv_gate* gates, size_t n_gates, const sv
   const auto t0 = std::chrono::steady_clock::now();
   std::vector<FusedGate> fused;
   std::vector<int32_t> block_of;
-  plan_fusion(gates, n_gates, s->n, o, fused, block_of, s->n >= kBlockCtrlMinQubits ? kBlockCtrl : 0);
+  plan_fusion(gates, n_gates, s->n, o, fused, block_of, block_ctrl(s->n, o.precision));
   const double fuse_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   run_passes(s, fused, o, stats);
   if (stats) {
@@ -607,7 +615,7 @@ int sv_fuse(const sv_gate* in, size_t n_in, int n_qubits, const sv_run_opts* opt
   try {
     std::vector<FusedGate> fused;
     std::vector<int32_t> block_of;
-    plan_fusion(in, n_in, n_qubits, o, fused, block_of, n_qubits >= kBlockCtrlMinQubits ? kBlockCtrl : 0);
+    plan_fusion(in, n_in, n_qubits, o, fused, block_of, block_ctrl(n_qubits, o.precision));
     // one allocation for the gate array, a second for all matrices
     size_t doubles = 0;
     for (auto& f : fused) doubles += f.mat.size();

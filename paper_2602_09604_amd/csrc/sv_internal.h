@@ -146,8 +146,9 @@ void fuse_blocks(const sv_gate* g, size_t n, const std::vector<std::vector<int>>
 constexpr int kCtrlMinBit = 7;
 constexpr uint64_t kCtrlLowBits = ((uint64_t)1 << kCtrlMinBit) - 1;
 // Controls a fused block takes when the search allows them, and the smallest
-// state where it does: a block with c controls runs as 2^c launches, each
-// over 2^-c of the state, which must still fill the GPU.
+// state where it does (with k < 4 targets a block with c controls runs as 2^c
+// register launches, each over 2^-c of the state, which must still fill the
+// GPU).
 constexpr int kBlockCtrl = 3;
 constexpr int kBlockCtrlMinQubits = 28;
 bool is_diagonal_gate(const sv_gate& g);

@@ -255,7 +255,7 @@ def test_learned_fusion_on_34_qubit_grid():
     reaches 49 and blocks with controls (CZs to outside qubits taken as
     control bits) at most 35 sweeps, with a valid partition."""
     gates = C.grid_circuit(2, 17, 24, seed=0)
-    fused, block_of = sv.sv_fuse(gates, 34, sv.make_opts(max_k=6, fusion="learned"))
+    fused, block_of = sv.sv_fuse(gates, 34, sv.make_opts(max_k=6, fusion="learned", precision="fp16x3"))
     assert check_partition(gates, fused, block_of, 6) <= 35
     ctrl = [f for f in fused if f.controls]
     assert ctrl and all(min(f.controls) >= 7 and len(f.controls) <= 3 for f in ctrl)
@@ -272,13 +272,15 @@ def test_blocks_with_controls_equivalent(rows, cols, depth, max_k, seed):
     checked on the circuit's own qubits."""
     n = rows * cols
     gates = C.grid_circuit(rows, cols, depth, seed=seed)
-    fused, block_of = sv.sv_fuse(gates, 30, sv.make_opts(max_k=max_k, fusion="learned"))
+    fused, block_of = sv.sv_fuse(gates, 30, sv.make_opts(max_k=max_k, fusion="learned", precision="fp16x3"))
     check_partition(gates, fused, block_of, max_k)
     assert any(f.controls for f in fused)
     block, _ = sv.sv_fuse(gates, 30, sv.make_opts(max_k=max_k, fusion="block"))
     assert sweeps(block_of) <= len(block)
-    small, small_of = sv.sv_fuse(gates, n, sv.make_opts(max_k=max_k, fusion="learned"))
+    small, _ = sv.sv_fuse(gates, n, sv.make_opts(max_k=max_k, fusion="learned", precision="fp16x3"))
     assert not any(f.controls for f in small)  # below 28 qubits no block takes controls
+    valu, _ = sv.sv_fuse(gates, 30, sv.make_opts(max_k=max_k, fusion="learned", precision="fp32_valu"))
+    assert not any(f.controls for f in valu)  # nor where the matrix cores do not run the blocks
     ref = oracle.apply_circuit(n, gates, init=seed + 5)
     assert np.max(np.abs(oracle.apply_circuit(n, fused, init=seed + 5) - ref)) < 1e-12
 
@@ -293,7 +295,7 @@ def test_block_split_rules():
     u = lambda k: C.haar_unitary(k, rng)  # noqa: E731
     gates = [C.Gate((0, 1), u(2)), C.Gate((1, 9), C.CZ), C.Gate((0, 1), u(2)), C.Gate((0, 8), C.CZ),
              C.Gate((0, 3), C.CZ), C.Gate((0, 1), u(2)), C.Gate((9,), u(1)), C.Gate((8,), u(1))]
-    fused, block_of = sv.sv_fuse(gates, 30, sv.make_opts(max_k=3, fusion="learned"))
+    fused, block_of = sv.sv_fuse(gates, 30, sv.make_opts(max_k=3, fusion="learned", precision="bf16x3"))
     assert check_partition(gates, fused, block_of, 3) == 2
     first = fused[0]
     assert first.controls == (8, 9) and first.qubits == (0, 1, 3)

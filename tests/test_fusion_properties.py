@@ -75,3 +75,55 @@ def test_fusion_is_exact(case, fusion, max_k):
     ref = oracle.apply_circuit(n, gates, init=init)
     got = oracle.apply_circuit(n, fused, init=init)
     assert np.max(np.abs(ref - got)) < 1e-11
+
+
+@st.composite
+def wide_circuits_st(draw):
+    """8..11 qubits, so that several qubits sit at bit 7 or above; many
+    diagonal two-qubit gates (CZ, CP) among dense and controlled ones."""
+    n = draw(st.integers(8, 11))
+    seed = draw(st.integers(0, 2**31 - 1))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gates = []
+    for _ in range(draw(st.integers(1, 50))):
+        kind = draw(st.sampled_from(["dense", "dense", "cz", "cp", "phase", "ctrl"]))
+        if kind == "dense":
+            k = int(rng.integers(1, 3))
+            qs = tuple(int(v) for v in rng.choice(n, k, replace=False))
+            gates.append(C.Gate(qs, C.haar_unitary(k, rng)))
+        elif kind in ("cz", "cp"):
+            a, b = (int(v) for v in rng.choice(n, 2, replace=False))
+            gates.append(C.Gate((a, b), C.CZ if kind == "cz" else C.CP(float(rng.uniform(0, 6.3)))))
+        elif kind == "phase":
+            gates.append(C.Gate((int(rng.integers(n)),), C.RZ(float(rng.uniform(0, 6.3)))))
+        else:
+            nc = int(rng.integers(1, 4))
+            qs = [int(v) for v in rng.choice(n, 1 + nc, replace=False)]
+            gates.append(C.Gate((qs[0],), C.haar_unitary(1, rng), tuple(qs[1:]),
+                                tuple(int(v) for v in rng.integers(0, 2, nc))))
+    return n, gates
+
+
+@settings(max_examples=150, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(wide_circuits_st(), st.integers(2, 6))
+def test_blocks_with_controls_are_exact(case, max_k):
+    """Learned fusion planned for a 30-qubit state at a matrix-core precision
+    (where blocks may take control bits): every block is one gate or 2^c gates
+    on the same targets with distinct control values, controls at bit 7 or
+    above, at most 3; the fused list acts exactly like the gate list."""
+    n, gates = case
+    fused, block_of = sv.sv_fuse(gates, 30, sv.make_opts(max_k=max_k, fusion="learned", precision="fp16x3"))
+    assert len(block_of) == len(gates)
+    starts = sorted(set(int(b) for b in block_of))
+    wide = {tuple(g.controls) for g in gates if g.controls}
+    for a, b in zip(starts, starts[1:] + [len(fused)]):
+        head = fused[a]
+        c = len(head.controls)
+        if c and tuple(head.controls) not in wide and b - a > 1:
+            assert b - a == 1 << c and c <= 3 and min(head.controls) >= 7
+            assert len({tuple(f.control_values) for f in fused[a:b]}) == b - a
+            assert all(f.qubits == head.qubits and f.controls == head.controls for f in fused[a:b])
+    init = int(np.random.Generator(np.random.PCG64(len(gates) + n)).integers(1 << n))
+    ref = oracle.apply_circuit(n, gates, init=init)
+    got = oracle.apply_circuit(n, fused, init=init)
+    assert np.max(np.abs(ref - got)) < 1e-11

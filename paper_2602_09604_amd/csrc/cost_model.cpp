@@ -178,9 +178,11 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
       }
     });
   };
-  // broad and narrow rule at max_k and max_k - 1, then the beam searches,
-  // then (when controls are allowed) the same at max_k with controls; sized
-  // before any thread starts so that the slots never move
+  // broad and narrow rule at max_k and max_k - 1, then (when controls are
+  // allowed) both rules at max_k with controls, then the beam searches, with
+  // controls when allowed (the beams without them found no fewer sweeps on
+  // any workload tried and cost half the search time); sized before any
+  // thread starts so that the slots never move
   const bool beam = n <= kBeamMaxGates;
   const int ctrl_rounds = max_ctrl > 0 ? 2 : 1;
   for (int r = 0; r < ctrl_rounds; ++r) {
@@ -190,7 +192,7 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
         blk.emplace_back();
         blk.back().ctrl = ctrl;
       }
-    for (int w = 0; beam && w < 2; ++w) {
+    for (int w = 0; beam && r == ctrl_rounds - 1 && w < 2; ++w) {
       blk.emplace_back();
       blk.back().ctrl = ctrl;
     }
@@ -204,7 +206,7 @@ bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int preci
           std::vector<std::vector<int>>* dst = &blk[i++].blocks;
           spawn([=] { maxblock_partition(g, n, K, narrow != 0, *dst, ctrl); });
         }
-      for (int w = 0; beam && w < 2; ++w) {  // beam searches over largest-block passes at max_k
+      for (int w = 0; beam && r == ctrl_rounds - 1 && w < 2; ++w) {  // beam searches at max_k
         std::vector<std::vector<int>>* dst = &blk[i++].blocks;
         const int width = kBeamWidths[w];
         spawn([=] { beam_partition(g, n, max_k, width, kBeamMoves, *dst, ctrl); });

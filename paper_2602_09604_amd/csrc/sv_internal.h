@@ -142,8 +142,9 @@ void beam_partition(const sv_gate* g, size_t n, int max_k, int width, int topm,
 void fuse_blocks(const sv_gate* g, size_t n, const std::vector<std::vector<int>>& blocks,
                  std::vector<FusedGate>& out, std::vector<int32_t>& block_of, int max_ctrl = 0);
 // Control bits a block may use: at or above kCtrlMinBit, so that every
-// control value covers runs of at least 2^7 amplitudes (1 KiB).
-constexpr int kCtrlMinBit = 7;
+// control value covers whole 128-byte lines (runs of at least 16 amplitudes)
+// and the matrix-core passes keep their streaming stores.
+constexpr int kCtrlMinBit = 4;
 constexpr uint64_t kCtrlLowBits = ((uint64_t)1 << kCtrlMinBit) - 1;
 // Controls a fused block takes when the search allows them, and the smallest
 // state where it does (with k < 4 targets a block with c controls runs as 2^c

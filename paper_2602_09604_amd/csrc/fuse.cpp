@@ -26,6 +26,7 @@
 #include <functional>
 #include <memory>
 #include <mutex>
+#include <stdexcept>
 #include <thread>
 #include <unordered_map>
 
@@ -235,6 +236,7 @@ static void build_block_mux(const sv_gate* g, const std::vector<int>& members, i
     build_block(g, members, outs.back());
     return;
   }
+  if (__builtin_popcountll(S) > SV_MAX_K) throw std::logic_error("block with controls wider than SV_MAX_K targets");
   int K = 0, bitpos[64], cbits[64], nc = 0;
   int q[SV_MAX_K];
   for (int b = 0; b < 64; ++b) {

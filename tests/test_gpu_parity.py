@@ -133,6 +133,36 @@ def test_graph_relaunch_and_replacement(own_stream):
         st.free()
 
 
+def test_graph_relaunch_of_blocks_with_controls():
+    """28 qubits, learned fusion at FP16X3 (blocks with control bits, one
+    matrix-core launch per block): the kept graph, relaunched, gives the
+    same state as plain launches, bit for bit, and keeps the norm."""
+    import torch
+    sv = _sv()
+    n = 28
+    gates = C.grid_circuit(4, 7, 10, seed=3)
+    fused, block_of = sv.sv_fuse(gates, n, sv.make_opts(max_k=6, fusion="learned", precision="fp16x3"))
+    assert any(f.controls for f in fused)
+    arr = sv.GateArray(gates)
+    kw = dict(max_k=6, fusion="learned", precision="fp16x3")
+    st = sv.State(n)
+    try:
+        st.apply_circuit(arr, **kw)
+        plain = st.read(0, 1 << 20)
+        plain_hi = st.read((1 << n) - (1 << 20), 1 << 20)
+        for rep in range(3):
+            st.set_basis(0)
+            s = st.apply_circuit(arr, use_graph=True, stats=True, **kw)
+            say("graph rep", rep, "relaunched", s["graph_relaunched"], "passes", s["passes"])
+            assert s["graph_relaunched"] == (rep > 0)
+            assert np.array_equal(st.read(0, 1 << 20), plain)
+            assert np.array_equal(st.read((1 << n) - (1 << 20), 1 << 20), plain_hi)
+        assert abs(st.norm() - 1.0) < 1e-5
+    finally:
+        st.free()
+        torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("max_k", [2, 3, 4, 5, 6])
 def test_grid_fused_greedy(max_k):
     n = 20

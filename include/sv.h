@@ -66,10 +66,16 @@ extern "C" {
  * that absorbs the most remaining gates (grown from every gate of the current
  * front), which needs far fewer passes than GREEDY on lattice circuits.
  * LEARNED scores candidate partitions (GREEDY for every k <= max_k,
- * cost-aware GREEDY variants, BLOCK, PHASE) with the cost-model network
- * loaded by sv_cost_model_load and keeps the cheapest; with no model loaded
- * it keeps the candidate with the fewest passes (every pass moves the same
- * bytes).  PHASE is GREEDY in which pure-phase diagonal gates of at
+ * cost-aware GREEDY variants, BLOCK, beam searches over BLOCK's passes,
+ * PHASE) with the cost-model network loaded by sv_cost_model_load and keeps
+ * the cheapest, unless it has more passes than the fewest-pass candidate and
+ * is predicted less than 5 % cheaper; with no model loaded it keeps the
+ * candidate with the fewest passes (every pass moves the same bytes).  For
+ * states of 28 qubits and more at BF16X3, FP16X3 or FP32_MFMA, LEARNED also
+ * lets a block take diagonal gates that reach up to 3 qubits outside its
+ * targets (at bit 4 or above) as control bits: such a block is one gate per
+ * control value on the same targets, and sv_apply_circuit runs all of them
+ * as one matrix-core launch when the block has k >= 4 targets.  PHASE is GREEDY in which pure-phase diagonal gates of at
  * most two qubits (CZ, CP, RZ, Z, S, T, ...) never block one another: those
  * that fit join dense blocks, the others are gathered into phase blocks of
  * any width.  sv_fuse returns a phase block as its canonical diagonal gates
@@ -203,7 +209,10 @@ int sv_apply_controlled_gate(sv_state* s, const int32_t* qubits, int k, const do
  * up to FP32 (or split-precision) rounding.  A controlled gate whose targets
  * and controls together span at most max_k qubits is lifted to a dense gate
  * on those qubits and fused (not with FUSE_NONE); a wider one is applied as
- * a controlled pass of its own, in FP32. */
+ * a controlled pass of its own: on the matrix cores at an MFMA precision when
+ * it has k >= 4 targets and at most 3 controls (none on bit 0), else in FP32.
+ * Consecutive controlled gates on the same targets and controls covering
+ * every control value (a fused block with controls) run as one launch. */
 int sv_apply_circuit(sv_state* s, const sv_gate* gates, size_t n_gates, const sv_run_opts* opts,
                      sv_run_stats* stats);
 
@@ -213,8 +222,9 @@ int sv_apply_circuit(sv_state* s, const sv_gate* gates, size_t n_gates, const sv
  * success *out is a library-allocated array of *n_out fused gates whose
  * qubits are ascending and whose matrices are the ordered products of the
  * absorbed gates lifted to the block's qubits; (*block_of_gate)[i] is the
- * index of the fused gate that absorbed input gate i.  Applying *out in order
- * equals applying `in` in order.  Free with sv_fused_free.  n_qubits bounds
+ * index of the fused gate that absorbed input gate i (for a block with
+ * control bits, which comes out as 2^c controlled gates, the first of them).
+ * Applying *out in order equals applying `in` in order.  Free with sv_fused_free.  n_qubits bounds
  * the qubit indices.  block_of_gate may be NULL. */
 int sv_fuse(const sv_gate* in, size_t n_in, int n_qubits, const sv_run_opts* opts, sv_gate** out,
             size_t* n_out, int32_t** block_of_gate);

@@ -182,11 +182,13 @@ def test_controlled_matrix_core_passes(case, prec):
     (18, (10, 11, 12, 13, 14, 15), (7, 8, 16), (5, 0, 7, 2, 1, 6, 3, 4), ()),
     (26, (9, 14, 20, 25), (7, 12, 22), tuple(range(8)), ()),
     (18, (1, 2, 3, 4), (7, 8), (0, 1, 2, 3), (2,)),   # one value missing: one launch per value
+    (18, (1, 2, 9), (7, 8, 17), tuple(range(8)), ()),  # k = 3: register launches, one per value
 ])
 def test_multiplexed_matrix_core_pass(case, prec):
     """One gate per control value on the same targets (what a fused block
     with controls becomes) runs as one matrix-core launch over the whole
-    state; a group with a value missing runs value by value."""
+    state; a group with a value missing, or with fewer than 4 targets, runs
+    value by value."""
     n, ts, cs, order, missing = case
     rng = np.random.Generator(np.random.PCG64(5 * n + len(cs)))
     gates = []
@@ -200,7 +202,10 @@ def test_multiplexed_matrix_core_pass(case, prec):
     try:
         st.apply_circuit(prep(n, 4), fusion="none")
         s = st.apply_circuit(gates, fusion="none", precision=prec, stats=True, timing=True)
-        if missing:
+        if len(ts) < 4:
+            assert s["passes"] == len(gates) and s["variant_passes"][1] == len(gates)
+            assert s["bytes"] == 16 << n  # 2^c launches over 2^-c of the state each
+        elif missing:
             assert s["passes"] == len(gates) and s["variant_passes"][3] == len(gates)
         else:
             assert s["passes"] == 1 and s["variant_passes"][3] == 1, s

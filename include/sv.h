@@ -129,10 +129,12 @@ typedef struct {
   int32_t use_graph;  /* 1: launch the passes as one hipGraph on the handle's
                          stream (captured on a private stream of the handle,
                          so any stream works).  The handle keeps the last graph and
-                         a device copy of its pass data; a later call whose
-                         passes and matrices encode to the same bytes relaunches
-                         it without capturing again.  A different circuit
-                         replaces it (the stream is synchronised first). */
+                         a device copy of its pass data.  A later call with the
+                         same gates, matrix values and options (and no cost
+                         model or tuned table loaded in between) relaunches it
+                         without fusing or uploading; one whose passes encode to
+                         the same bytes relaunches it after fusing.  A different
+                         circuit replaces it (the stream is synchronised first). */
   int32_t variant;    /* SV_VARIANT_* (AUTO unless a test forces one) */
   int32_t timing;     /* 1: bracket every pass with HIP events on the handle's
                          stream and report per-variant device time in stats

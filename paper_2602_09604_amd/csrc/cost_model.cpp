@@ -89,9 +89,12 @@ void cost_features(int k, const int* qubits, int n, int precision, float* out) {
 }
 
 void cost_model_set(const std::vector<float>& params, int width) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  g_params = params;
-  g_width = width;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_params = params;
+    g_width = width;
+  }
+  bump_plan_epoch();
 }
 
 bool cost_model_ready() {

@@ -203,6 +203,11 @@ void launch_marginal(const void* psi, int n, int m, const int* qubits, double* s
 size_t sample_scratch_bytes(int n);
 void launch_sample(const void* psi, int n, bool prepare, const double* uniforms, uint64_t shots, uint64_t* out,
                    double* scratch, hipStream_t st);
+// Planning epoch: bumped whenever something fusion or variant choice reads
+// changes (the installed cost model, the tuned launch table), so that a kept
+// graph is never relaunched for a plan that would now come out different.
+uint64_t plan_epoch();
+void bump_plan_epoch();
 // Learned fusion; max_ctrl > 0 adds candidates whose blocks take controls.
 bool fuse_learned(const sv_gate* g, size_t n, int n_qubits, int max_k, int precision,
                   std::vector<FusedGate>& out, std::vector<int32_t>& block_of, int max_ctrl);

@@ -238,6 +238,7 @@ int sv_autotune(sv_state* s, int budget_ms) {
       std::lock_guard<std::mutex> lk(g_mu);
       for (auto& kv : found) g_table[kv.first] = kv.second;
     }
+    bump_plan_epoch();
     (void)hipFree(dev);
     (void)hipHostFree(host);
     (void)hipEventDestroy(e0);
@@ -315,8 +316,11 @@ int sv_tune_load(const char* path) {
         return fail(SV_EINVAL, "batch_lds_max_n out of range");
       set_batch_lds_max_n(v);
     }
-    std::lock_guard<std::mutex> lk(g_mu);
-    for (auto& kv : parsed) g_table[kv.first] = kv.second;
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      for (auto& kv : parsed) g_table[kv.first] = kv.second;
+    }
+    bump_plan_epoch();
     return SV_OK;
   });
 }

@@ -100,7 +100,7 @@ def test_config1_grid_unfused_full_state():
 
 
 @pytest.mark.parametrize("own_stream", [False, True])
-def test_graph_relaunch_and_replacement(own_stream):
+def test_graph_relaunch_and_replacement(own_stream, tmp_path):
     """use_graph keeps its graph: the same circuit again relaunches it, plain
     calls in between (which reuse the upload ring) leave its pass data alone,
     and a different circuit replaces it.  The state after the whole sequence
@@ -124,10 +124,20 @@ def test_graph_relaunch_and_replacement(own_stream):
         seq = []
         for name, kw, relaunched in runs:
             s = st.apply_circuit(arrays[name], stats=True, **kw)
-            say(name, kw, "relaunched", s["graph_relaunched"])
+            say(name, kw, "relaunched", s["graph_relaunched"], "fuse_s", s["fuse_s"])
             if relaunched is not None:
                 assert s["graph_relaunched"] == relaunched
+                if relaunched:  # the same call again: no fusion, no upload
+                    assert s["fuse_s"] == 0.0 and s["passes"] > 0 and s["bytes"] > 0
             seq += a if name == "a" else b
+        # reloading the tuned table (unchanged) bumps the planning epoch: the
+        # next identical call plans again, then finds the same passes
+        path = str(tmp_path / "tune.json")
+        sv.sv_tune_save(path)
+        sv.sv_tune_load(path)
+        s = st.apply_circuit(arrays["a"], stats=True, **runs[-1][1])
+        assert s["fuse_s"] > 0.0 and s["graph_relaunched"] == 1
+        seq += a
         check(st.read(), oracle.apply_circuit(n, seq))
     finally:
         st.free()

@@ -174,7 +174,7 @@ def test_controlled_matrix_core_passes(case, prec):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("prec", ["fp16x3", "fp32_mfma"])
+@pytest.mark.parametrize("prec", ["fp16x3", "bf16x3", "fp32_mfma"])
 @pytest.mark.parametrize("case", [
     # (n, targets, controls, order of the control values given, values left out)
     (16, (2, 3, 5, 9), (12,), (1, 0), ()),
@@ -183,6 +183,8 @@ def test_controlled_matrix_core_passes(case, prec):
     (26, (9, 14, 20, 25), (7, 12, 22), tuple(range(8)), ()),
     (18, (1, 2, 3, 4), (7, 8), (0, 1, 2, 3), (2,)),   # one value missing: one launch per value
     (18, (1, 2, 9), (7, 8, 17), tuple(range(8)), ()),  # k = 3: register launches, one per value
+    (15, (0, 1, 2, 3, 4, 5), (12, 13, 14), tuple(range(8)), ()),  # smallest states: a few tiles per value
+    (16, (1, 2, 3, 4, 5, 6), (13, 14, 15), (7, 6, 5, 4, 3, 2, 1, 0), ()),
 ])
 def test_multiplexed_matrix_core_pass(case, prec):
     """One gate per control value on the same targets (what a fused block

@@ -243,3 +243,45 @@ def test_flop_and_ai_accounting():
     assert abs(paper_ai(1, ai["numVals"]) - ai["unfused_approx"]) < 0.01
     for f in range(1, 7):
         assert abs(2 * paper_ai(f, 4) - ai_read_write(f)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# The comparison statistics themselves, on vectors exactly representable in
+# complex64, against values worked out by hand.
+# ---------------------------------------------------------------------------
+def test_compare_statistics_by_hand():
+    o = np.array([0.5, 0.5j, -0.5, 0.5], dtype=np.complex128)  # norm 1
+    # g = 2 o: parallel, so no infidelity; |g - o| = |o|; <g|g> = 4
+    r = oracle.compare((2 * o).astype(np.complex64), o)
+    assert r["max_abs"] == 0.5 and r["rel_l2"] == 1.0
+    assert r["infidelity"] == 0.0 and r["norm_drift"] == 3.0
+    # one sign flipped: <o|g> = 0.25 + 0.25 - 0.25 + 0.25 = 0.5, fidelity 1/4;
+    # the difference is 1 at one index, the norm unchanged
+    g = np.array([0.5, 0.5j, 0.5, 0.5], dtype=np.complex64)
+    r = oracle.compare(g, o)
+    assert r["max_abs"] == 1.0 and r["rel_l2"] == 1.0
+    assert r["infidelity"] == 0.75 and r["norm_drift"] == 0.0
+    # a global phase i: fidelity 1, |i c - c| = sqrt(2) |c|
+    r = oracle.compare((1j * o).astype(np.complex64), o)
+    assert r["infidelity"] == 0.0 and r["norm_drift"] == 0.0
+    assert abs(r["rel_l2"] - np.sqrt(2.0)) < 1e-15 and abs(r["max_abs"] - 0.5 * np.sqrt(2.0)) < 1e-15
+
+
+def test_compare_streaming_equals_one_shot():
+    rng = np.random.Generator(np.random.PCG64(17))
+    o = rng.standard_normal(1000) + 1j * rng.standard_normal(1000)
+    o /= np.linalg.norm(o)
+    g = (o + 1e-4 * (rng.standard_normal(1000) + 1j * rng.standard_normal(1000))).astype(np.complex64)
+    one = oracle.compare(g, o)
+    acc = oracle.CompareAcc()
+    for a, b in ((0, 137), (137, 600), (600, 1000)):
+        acc.add(g[a:b], o[a:b])
+    part = acc.result()
+    for key in ("max_abs", "rel_l2", "infidelity", "norm_drift"):
+        assert abs(part[key] - one[key]) <= 1e-12 * max(1.0, abs(one[key])), key
+    # and against numpy written out directly
+    gd = g.astype(np.complex128)
+    assert abs(one["rel_l2"] - np.linalg.norm(gd - o)) < 1e-12
+    assert abs(one["norm_drift"] - abs(np.vdot(gd, gd).real - 1.0)) < 1e-12
+    fid = abs(np.vdot(o, gd)) ** 2 / (np.vdot(o, o).real * np.vdot(gd, gd).real)
+    assert abs(one["infidelity"] - (1.0 - fid)) < 1e-12

@@ -238,6 +238,26 @@ int sv_fused_free(sv_gate* fused, size_t n, int32_t* block_of_gate);
  * two-level block reduction.  Synchronises the handle's stream. */
 int sv_norm(sv_state* s, double* norm_sq);
 
+/* sv_norm for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): no
+ * handle, no allocation, no synchronisation.  Enqueues on hip_stream (a
+ * hipStream_t, NULL for the default stream) the same two-level FP64
+ * reduction sum_i |c_i|^2 as sv_norm over the complex64 state at dev_state
+ * (re/im interleaved, 8 * 2^n_qubits bytes within buf_bytes, 16-byte
+ * aligned, caller-owned) and writes the result to the device double at
+ * dev_out (caller-owned, 8-byte aligned) when the stream reaches it.  Both
+ * pointers must be device memory on the calling thread's current device.
+ * The first-level partials live in a static per-device scratch of 2048
+ * doubles (16 KiB, held by each device the library runs on until the
+ * process ends); every call writes the partials it reads, so nothing has
+ * to be cleared.  Every call on one device shares that scratch: calls whose
+ * execution overlaps on one GPU (on different streams) race.  States of
+ * 1..40 qubits (SV_MAX_QUBITS); anything else is SV_EINVAL.  Errors:
+ * SV_EINVAL (NULL, bad alignment, n_qubits outside 1..40, buf_bytes <
+ * 8 * 2^n, a pointer that is not device memory on the current device),
+ * SV_EDEVICE (a launch failed). */
+int sv_norm_noalloc(const void* dev_state, int n_qubits, size_t buf_bytes, void* hip_stream, double* dev_out);
+
 /* Expectation values of Pauli strings (the paper's expectation-value kernel,
  * Sec. IV: a read of the state that writes nothing back).  Term t is the
  * string with X on the qubits of xmask[t] only, Z on zmask[t] only and Y on

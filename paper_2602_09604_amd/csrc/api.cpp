@@ -748,6 +748,34 @@ int sv_norm(sv_state* s, double* norm_sq) {
   SV_GUARD_END(s)
 }
 
+int sv_norm_noalloc(const void* dev_state, int n_qubits, size_t buf_bytes, void* hip_stream, double* dev_out) {
+  if (!dev_state || !dev_out) return fail(SV_EINVAL, "dev_state / dev_out is NULL");
+  if (n_qubits < 1 || n_qubits > SV_MAX_QUBITS) return fail(SV_EINVAL, "n_qubits must be 1..40");
+  const size_t need = (size_t)8 << n_qubits;
+  if (buf_bytes < need)
+    return fail(SV_EINVAL, "buffer holds " + std::to_string(buf_bytes) + " bytes, need " + std::to_string(need));
+  if (((uintptr_t)dev_state & 15) != 0) return fail(SV_EINVAL, "dev_state must be 16-byte aligned");
+  if (((uintptr_t)dev_out & 7) != 0) return fail(SV_EINVAL, "dev_out must be 8-byte aligned");
+  try {
+    int dev = 0;
+    SV_HIP(hipGetDevice(&dev));
+    for (const void* p : {dev_state, static_cast<const void*>(dev_out)}) {
+      hipPointerAttribute_t attr{};
+      if (hipPointerGetAttributes(&attr, p) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        return fail(SV_EINVAL, "dev_state and dev_out must be device memory");
+      }
+      if (attr.device != dev) return fail(SV_EINVAL, "dev_state and dev_out must be on the current device");
+    }
+    launch_norm_noalloc(dev_state, n_qubits, dev_out, (hipStream_t)hip_stream);
+    return SV_OK;
+  } catch (const DeviceError& e) {
+    return fail(SV_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.err));
+  } catch (...) {
+    return fail(SV_EDEVICE, "unknown failure");
+  }
+}
+
 int sv_expect_pauli(sv_state* s, size_t n_terms, const uint64_t* xmask, const uint64_t* zmask, double* out) {
   if (int rc = check_handle(s)) return rc;
   if (n_terms == 0) return SV_OK;

@@ -1,4 +1,6 @@
 // State initialisation and the FP64 norm reduction sum |c_i|^2 (Eq. 1).
+#include <mutex>
+
 #include "k_common.h"
 
 namespace sv {
@@ -84,9 +86,43 @@ __global__ void k_norm_1q(const float2* __restrict__ psi, double* __restrict__ o
   }
 }
 
+// Scratch of the allocation-free norm: the first-level partials, one copy per
+// device (the runtime places it when the code object loads; it stays until the
+// process ends).  Host code never passes this name to a kernel: it is a host
+// stand-in, not a device address.  The device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+static __device__ __align__(256) double scratch[kNormBlocks];
+
 }  // namespace
 
 int norm_partials_needed() { return kNormBlocks; }
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of `scratch` on the current device (looked up on the first
+// call per device).
+static double* scratch_on_current_device() {
+  int dev = 0;
+  SV_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw DeviceError{hipErrorInvalidDevice, "scratch: device index"};
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    SV_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
+void launch_norm_noalloc(const void* psi, int n, double* out, hipStream_t st) {
+  // launch_norm caps its first level at kNormBlocks partials and writes every
+  // partial the second level reads, so the scratch needs no clearing
+  launch_norm(psi, n, scratch_on_current_device(), kNormBlocks, out, st);
+}
 
 void launch_init_basis(void* psi, int n, uint64_t index, hipStream_t st) {
   if (n == 1) {

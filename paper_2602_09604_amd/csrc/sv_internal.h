@@ -87,6 +87,9 @@ void launch_pass(const Pass& p, int n, void* psi, const unsigned char* arena_dev
 void launch_init_basis(void* psi, int n, uint64_t index, hipStream_t st);
 void launch_norm(const void* psi, int n, double* partials, int max_parts, double* out, hipStream_t st);
 int norm_partials_needed();
+// The same reduction with its partials in the library's static per-device
+// scratch (no allocation); `out` is a device double.
+void launch_norm_noalloc(const void* psi, int n, double* out, hipStream_t st);
 
 // Bytes of device data a pass needs in the arena for its precision/variant,
 // and the host-side encoder that writes it (matrix already normalised,

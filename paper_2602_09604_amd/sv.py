@@ -85,6 +85,7 @@ _SIGS = {
                                ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_i32p)]),
     "sv_fused_free": (ctypes.c_int, [ctypes.POINTER(sv_gate), ctypes.c_size_t, _i32p]),
     "sv_norm": (ctypes.c_int, [_vp, _dp]),
+    "sv_norm_noalloc": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_size_t, _vp, _vp]),
     "sv_read_amplitudes": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_uint64, _fp]),
     "sv_write_amplitudes": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_uint64, _fp]),
     "sv_batch_run": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(ctypes.POINTER(sv_gate)),

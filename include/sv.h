@@ -52,8 +52,11 @@ extern "C" {
  * [Yr;Yi] = [[Ur,-Ui],[Ui,Ur]] [Xr;Xi] on FP32 matrix cores.
  * BF16X3 / FP16X3: the same GEMM with every operand split into hi + lo
  * halves of the narrow type and three products (hi*hi + hi*lo + lo*hi)
- * accumulated in FP32; FP16X3 scales amplitudes by 2^14 before the split
- * (valid for normalised states, |c| <= 1). */
+ * accumulated in FP32; FP16X3 scales amplitudes by 2^14 before the split,
+ * so it needs |c| < ~4: sv_apply_circuit at FP16X3 rejects (SV_EINVAL) a
+ * circuit with a gate that is not unitary, or a state whose sum |c|^2 may
+ * exceed 15 (after sv_write_amplitudes or a non-unitary gate it measures the
+ * sum once with one read sweep before deciding). */
 #define SV_PREC_FP32_VALU 0
 #define SV_PREC_FP32_MFMA 1
 #define SV_PREC_BF16X3 2
@@ -161,7 +164,8 @@ typedef struct {
 
 /* ---- state -------------------------------------------------------------- */
 
-/* Wrap a caller-owned device buffer as an n-qubit complex64 state and write
+/* The state of Sec. II-A, Eq. 1: 2^n complex amplitudes, here complex64.
+ * Wrap a caller-owned device buffer as an n-qubit complex64 state and write
  * |0...0> into it (asynchronously on `hip_stream`, a hipStream_t or NULL for
  * the default stream).  dev_buf must hold at least 8 * 2^n bytes and stay
  * valid until sv_free; it is never freed by the library.  1 <= n <= 40.
@@ -175,8 +179,9 @@ int sv_alloc(int n_qubits, int dtype, void* dev_buf, size_t buf_bytes, void* hip
  * Never frees the borrowed state buffer.  NULL is accepted. */
 int sv_free(sv_state* s);
 
-/* Overwrite the state with the basis state |index> (asynchronous).
- * SV_EINVAL if index >= 2^n. */
+/* Overwrite the state with the basis state |index> (Eq. 1 with the single
+ * amplitude c_index = 1; the basis-state inputs of the Sec. VI circuits),
+ * asynchronously.  SV_EINVAL if index >= 2^n. */
 int sv_set_basis(sv_state* s, uint64_t index);
 
 /* Number of qubits of a handle (or SV_EINVAL for NULL). */
@@ -282,23 +287,34 @@ int sv_marginal_probs(sv_state* s, int n_meas, const int32_t* qubits, double* ou
  * zero state. */
 int sv_sample(sv_state* s, size_t n_shots, const double* uniforms, uint64_t* out);
 
-/* Copy amplitudes [start, start + count) to host memory as complex64
- * (2*count floats, re/im interleaved), in chunks of 2^26 amplitudes.
- * Synchronous.  SV_EINVAL if start + count > 2^n or host_out is NULL. */
+/* Read-back of the final state vector, which Sec. VI compares amplitude by
+ * amplitude with a reference simulator.  Copy amplitudes [start, start +
+ * count) to host memory as complex64 (2*count floats, re/im interleaved,
+ * caller-owned), in chunks of 2^26 amplitudes.  Synchronous.  SV_EINVAL if
+ * start + count > 2^n or host_out is NULL. */
 int sv_read_amplitudes(sv_state* s, uint64_t start, uint64_t count, float* host_out);
 
-/* Copy amplitudes from host (complex64, interleaved) into [start, start+count).
- * Synchronous.  Used to load a prepared state or a checkpoint. */
+/* Load amplitudes of a prepared state (any linear combination of Eq. 1; it
+ * need not be normalised) or of a checkpoint: copy 2*count floats from host
+ * (complex64, interleaved, caller-owned) into [start, start+count).
+ * Synchronous.  SV_EINVAL if start + count > 2^n or host_in is NULL. */
 int sv_write_amplitudes(sv_state* s, uint64_t start, uint64_t count, const float* host_in);
 
 /* ---- batching ------------------------------------------------------------ */
 
-/* Run n_circuits independent circuits, circuit c on states[c] (each handle on
- * the same device; the stream of states[0] is used), as one launch of the
- * batched persistent kernel captured in a hipGraph.  Circuits whose state
- * fits in LDS (n <= 14) are simulated entirely on chip; larger ones are
- * swept through HBM by the same kernel with a per-circuit barrier between
- * fused gates.  Gates are fused first per opts (fusion mode and max_k; GREEDY
+/* Many independent circuits at once: the group parallelism of Sec. IV
+ * (every group of every circuit's pass is independent) spread over a whole
+ * batch, with each circuit fused as in Sec. II-C.  Runs n_circuits circuits,
+ * circuit c on states[c] (each handle on the same device).  The work is
+ * queued on the stream of states[0], after the work already queued on the
+ * other handles' streams; the call returns once it has finished.  All
+ * launches are captured in one hipGraph: circuits whose state fits in LDS
+ * (n <= the autotuned limit, at most 13 qubits = 64 KiB) run in one
+ * workgroup each, entirely on chip, with one HBM read and one write;
+ * larger ones advance one fused pass per launch of a level kernel that
+ * covers that pass of every circuit that has one (the kernel boundary is
+ * the barrier between a circuit's dependent passes).  On a device failure
+ * every handle in the batch is poisoned.  Gates are fused first per opts (fusion mode and max_k; GREEDY
  * with max_k 4 when opts is NULL; the precision is always FP32), circuits on
  * host threads.  A controlled gate wider than max_k with its controls is
  * rejected (SV_EINVAL).  States of at most 30 qubits.  When stats is not NULL
@@ -351,6 +367,10 @@ int sv_mlp_train(sv_mlp* m, const float* x_dev, const float* y_dev, int n, int e
 int sv_cost_model_install(sv_mlp* m);
 int sv_cost_model_save(const char* path);
 int sv_cost_model_load(const char* path);
+/* Remove the installed cost model: SV_FUSE_LEARNED then runs the same
+ * candidate search and keeps the partition with the fewest passes (what the
+ * method does without the network).  Always SV_OK. */
+int sv_cost_model_clear(void);
 /* Host-side prediction of log(pass seconds / 2^n) for a gate (k, qubits,
  * n, precision) under the installed model: what the partition search uses. */
 int sv_cost_model_predict(int k, const int32_t* qubits, int n_qubits, int precision, double* out);

@@ -3,6 +3,7 @@
 #include <atomic>
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -46,6 +47,11 @@ struct sv_state {
   size_t meas_cap = 0;
   unsigned char* meas_host = nullptr;  // pinned
   size_t meas_host_cap = 0;
+  // sum |c_i|^2 of the state as far as the host knows it once the queued
+  // work has run (basis states and unitary passes keep 1; sv_norm measures
+  // it); negative when unknown (after sv_write_amplitudes or a gate that is
+  // not unitary).  FP16X3 passes need it bounded (see fp16x3_range_ok).
+  double norm_known = 1.0;
 };
 
 namespace sv {
@@ -475,6 +481,31 @@ using namespace sv;
     return fail(SV_EINVAL, "unknown failure");                                                \
   }
 
+// FP16X3 scales amplitudes by 2^14 before rounding to fp16 (largest finite
+// 65504): |c| must stay below ~3.99.  Every |c| <= sqrt(sum |c|^2), so a
+// state with sum |c|^2 <= 15 is safe, and unitary passes keep that sum.
+static constexpr double kFp16x3MaxNormSq = 15.0;
+
+// Every gate unitary to 1e-6 per entry of U^dagger U - I (FP64, host).
+static bool gates_unitary(const sv_gate* g, size_t n) {
+  for (size_t i = 0; i < n; ++i) {
+    const int d = 1 << g[i].k;
+    const double* m = g[i].matrix;
+    for (int a = 0; a < d; ++a)
+      for (int b = a; b < d; ++b) {
+        double re = 0.0, im = 0.0;  // (U^dagger U)[a][b] = sum_r conj(U[r][a]) U[r][b]
+        for (int r = 0; r < d; ++r) {
+          const double ar = m[2 * (r * d + a)], ai = m[2 * (r * d + a) + 1];
+          const double br = m[2 * (r * d + b)], bi = m[2 * (r * d + b) + 1];
+          re += ar * br + ai * bi;
+          im += ar * bi - ai * br;
+        }
+        if (std::fabs(re - (a == b ? 1.0 : 0.0)) > 1e-6 || std::fabs(im) > 1e-6) return false;
+      }
+  }
+  return true;
+}
+
 static int check_handle(sv_state* s) {
   if (!s) return fail(SV_EINVAL, "state handle is NULL");
   if (s->poisoned) return fail(SV_ESTATE, "handle poisoned by an earlier device failure");
@@ -564,6 +595,7 @@ int sv_set_basis(sv_state* s, uint64_t index) {
   SV_GUARD_BEGIN
   SV_HIP(hipSetDevice(s->device));
   launch_init_basis(s->psi, s->n, index, s->stream);
+  s->norm_known = 1.0;
   return SV_OK;
   SV_GUARD_END(s)
 }
@@ -585,6 +617,7 @@ int sv_apply_gate(sv_state* s, const int32_t* qubits, int k, const double* matri
   sv_run_opts o = default_opts();
   o.fusion = SV_FUSE_NONE;
   run_passes(s, fused, o, nullptr);
+  if (!gates_unitary(&g, 1)) s->norm_known = -1.0;
   return SV_OK;
   SV_GUARD_END(s)
 }
@@ -617,6 +650,7 @@ int sv_apply_controlled_gate(sv_state* s, const int32_t* qubits, int k, const do
   sv_run_opts o = default_opts();
   o.fusion = SV_FUSE_NONE;
   run_passes(s, fused, o, nullptr);
+  if (!gates_unitary(&g, 1)) s->norm_known = -1.0;
   return SV_OK;
   SV_GUARD_END(s)
 }
@@ -627,8 +661,24 @@ int sv_apply_circuit(sv_state* s, const sv_gate* gates, size_t n_gates, const sv
   const sv_run_opts o = opts ? *opts : default_opts();
   if (int rc = check_opts(o)) return rc;
   if (int rc = validate_gates(gates, n_gates, s->n)) return rc;
+  const bool unitary = gates_unitary(gates, n_gates);
+  if (o.precision == SV_PREC_FP16X3 && !unitary)
+    return fail(SV_EINVAL, "FP16X3 needs unitary gates (a gate's U^dagger U differs from I by more than 1e-6): "
+                           "use FP32_MFMA or BF16X3");
   SV_GUARD_BEGIN
   SV_HIP(hipSetDevice(s->device));
+  if (o.precision == SV_PREC_FP16X3) {
+    if (s->norm_known < 0.0) {  // measure it once (one read sweep)
+      launch_norm(s->psi, s->n, s->partials, norm_partials_needed(), s->norm_dev, s->stream);
+      SV_HIP(hipMemcpyAsync(s->norm_host, s->norm_dev, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+      SV_HIP(hipStreamSynchronize(s->stream));
+      s->norm_known = *s->norm_host;
+    }
+    if (!(s->norm_known <= kFp16x3MaxNormSq))
+      return fail(SV_EINVAL, "FP16X3 needs sum |c|^2 <= 15 (amplitudes above ~4 overflow fp16 after the 2^14 "
+                             "scale); the state has " + std::to_string(s->norm_known) + ": use FP32_MFMA or BF16X3");
+  }
+  if (!unitary) s->norm_known = -1.0;
   if (stats) *stats = sv_run_stats{};
   const bool graph = o.use_graph && !(o.timing && stats);
   std::vector<unsigned char> key;
@@ -744,6 +794,7 @@ int sv_norm(sv_state* s, double* norm_sq) {
   SV_HIP(hipMemcpyAsync(s->norm_host, s->norm_dev, sizeof(double), hipMemcpyDeviceToHost, s->stream));
   SV_HIP(hipStreamSynchronize(s->stream));
   *norm_sq = *s->norm_host;
+  s->norm_known = *norm_sq;
   return SV_OK;
   SV_GUARD_END(s)
 }
@@ -923,6 +974,7 @@ int sv_write_amplitudes(sv_state* s, uint64_t start, uint64_t count, const float
                           s->stream));
   }
   SV_HIP(hipStreamSynchronize(s->stream));
+  if (count) s->norm_known = -1.0;
   return SV_OK;
   SV_GUARD_END(s)
 }
@@ -936,4 +988,9 @@ int state_n(sv_state* s) { return s->n; }
 hipStream_t state_stream(sv_state* s) { return s->stream; }
 bool state_poisoned(sv_state* s) { return s->poisoned; }
 void state_poison(sv_state* s) { s->poisoned = true; }
+// After a batched run: a circuit with a gate that is not unitary leaves the
+// state's norm unknown to the host.
+void state_note_gates(sv_state* s, const sv_gate* g, size_t n) {
+  if (!gates_unitary(g, n)) s->norm_known = -1.0;
+}
 }  // namespace sv

@@ -358,6 +358,13 @@ int sv_cost_model_load(const char* path) {
   });
 }
 
+int sv_cost_model_clear(void) {
+  return host_guard([&]() -> int {
+    cost_model_set(std::vector<float>(), 0);
+    return SV_OK;
+  });
+}
+
 int sv_cost_model_predict(int k, const int32_t* qubits, int n_qubits, int precision, double* out) {
   return host_guard([&]() -> int {
     if (!qubits || !out || k < 1 || k > SV_MAX_K || n_qubits < 1 || n_qubits > SV_MAX_QUBITS)

@@ -34,6 +34,7 @@ int state_n(sv_state* s);
 hipStream_t state_stream(sv_state* s);
 bool state_poisoned(sv_state* s);
 void state_poison(sv_state* s);
+void state_note_gates(sv_state* s, const sv_gate* g, size_t n);
 
 namespace {
 using namespace kern;
@@ -410,11 +411,28 @@ extern "C" int sv_batch_run(sv_state* const* states, const sv_gate* const* circu
   }
   // batched passes run on the VALU kernels; the precision field only selects FP32
   o.precision = SV_PREC_FP32_VALU;
+  std::vector<hipEvent_t> waits;
   try {
+    // work already queued on the other handles' streams (initialisation,
+    // earlier passes) must finish before the batch touches their states
+    const hipStream_t st0 = state_stream(states[0]);
+    std::vector<hipStream_t> seen{st0};
+    for (size_t c = 1; c < n_circuits; ++c) {
+      const hipStream_t sc = state_stream(states[c]);
+      if (std::find(seen.begin(), seen.end(), sc) != seen.end()) continue;
+      seen.push_back(sc);
+      hipEvent_t ev = nullptr;
+      SV_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      waits.push_back(ev);
+      SV_HIP(hipEventRecord(ev, sc));
+      SV_HIP(hipStreamWaitEvent(st0, ev, 0));
+    }
     double gpu_s = 0, fuse_s = 0;
     uint64_t np = 0;
-    batch_run_impl(psis.data(), ns.data(), circuits, n_gates, n_circuits, o, state_stream(states[0]), -1, &gpu_s,
-                   &np, &fuse_s);
+    batch_run_impl(psis.data(), ns.data(), circuits, n_gates, n_circuits, o, st0, -1, &gpu_s, &np, &fuse_s);
+    for (hipEvent_t ev : waits) (void)hipEventDestroy(ev);
+    waits.clear();
+    for (size_t c = 0; c < n_circuits; ++c) state_note_gates(states[c], circuits[c], n_gates[c]);
     if (stats) {
       *stats = sv_run_stats{};
       uint64_t gi = 0;
@@ -426,13 +444,17 @@ extern "C" int sv_batch_run(sv_state* const* states, const sv_gate* const* circu
     }
     return SV_OK;
   } catch (const DeviceError& e) {
-    state_poison(states[0]);
+    for (hipEvent_t ev : waits) (void)hipEventDestroy(ev);
+    for (size_t c = 0; c < n_circuits; ++c) state_poison(states[c]);
     return fail(SV_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.err));
   } catch (const std::bad_alloc&) {
+    for (hipEvent_t ev : waits) (void)hipEventDestroy(ev);
     return fail(SV_ENOMEM, "host allocation failed");
   } catch (const std::exception& e) {
+    for (hipEvent_t ev : waits) (void)hipEventDestroy(ev);
     return fail(SV_EINVAL, e.what());
   } catch (...) {
+    for (hipEvent_t ev : waits) (void)hipEventDestroy(ev);
     return fail(SV_EINVAL, "unknown failure");
   }
 }

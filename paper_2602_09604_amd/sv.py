@@ -106,6 +106,7 @@ _SIGS = {
     "sv_cost_model_install": (ctypes.c_int, [_vp]),
     "sv_cost_model_save": (ctypes.c_int, [ctypes.c_char_p]),
     "sv_cost_model_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "sv_cost_model_clear": (ctypes.c_int, []),
     "sv_cost_model_predict": (ctypes.c_int, [ctypes.c_int, _i32p, ctypes.c_int, ctypes.c_int, _dp]),
     "sv_cost_features": (ctypes.c_int, [ctypes.c_int, _i32p, ctypes.c_int, ctypes.c_int, _fp]),
     "sv_last_error": (ctypes.c_char_p, []),
@@ -388,6 +389,10 @@ def sv_cost_model_save(path: str) -> None:
 
 def sv_cost_model_load(path: str) -> None:
     _check(lib().sv_cost_model_load(os.fsencode(path)))
+
+
+def sv_cost_model_clear() -> None:
+    _check(lib().sv_cost_model_clear())
 
 
 def sv_cost_model_predict(k: int, qubits, n: int, precision: int) -> float:

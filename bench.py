@@ -71,6 +71,131 @@ def counter_traffic(kernel: str, workload_name: str, alg_bytes_per_launch: float
     return float(m.group(1)) * alg_bytes_per_launch
 
 
+def host_info() -> dict:
+    """CPU model, logical CPUs and RAM of the host the oracle runs on."""
+    model, mem = "unknown", 0
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                mem = int(line.split()[1]) * 1024
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "ram_GiB": round(mem / 2 ** 30, 1)}
+
+
+GOLDEN = {"grid34": "grid34_d24_s0_cut.npz", "grid30": "grid30_d20_s0.npz"}
+
+
+def accuracy_vs_oracle(st, workload_name: str):
+    """Sampled amplitudes of the state against the stored oracle values for
+    this workload (tests/golden: exact amplitudes the oracle computed, by a
+    two-way cut of the 34-qubit ladder or on the full 30-qubit state), or
+    None when there is no stored file."""
+    import numpy as np
+    name = GOLDEN.get(workload_name)
+    path = os.path.join(ROOT, "tests", "golden", name) if name else None
+    if not path or not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as f:
+        idx, ref, nr = f["idx"], f["amp"], int(f["n_random"])
+    got_r = np.array([st.read(int(i), 1)[0] for i in idx[:nr]], dtype=np.complex64)
+    got_b = st.read(int(idx[nr]), idx.size - nr)
+    got = np.concatenate([got_r, got_b]).astype(np.complex128)
+    d = got - ref
+    o2, g2 = float(np.vdot(ref, ref).real), float(np.vdot(got, got).real)
+    fid = abs(np.vdot(ref, got)) ** 2 / (o2 * g2)
+    return {"samples": int(idx.size), "max_abs": float(np.max(np.abs(d))),
+            "rel_l2": float(np.sqrt(np.vdot(d, d).real / o2)), "sampled_infidelity": float(1.0 - fid),
+            "reference": "tests/golden/" + name}
+
+
+def issued_mfma_flops(gates, n: int, max_k: int, fusion: str, precision: str) -> dict:
+    """Useful and issued flops of one run's matrix-core passes, from the
+    partition sv_fuse returns for the same options (the model installed at
+    the time of the call decides it, as in sv_apply_circuit).  A pass on k
+    targets covering g groups is a real 4M-form GEMM of 2^(k+1) x 2^(k+1)
+    by 2^(k+1) x g: 2 * 4^(k+1) * g flops per product, three products in the
+    split modes; useful flops are g * 2^k (8 * 2^k - 2)."""
+    from paper_2602_09604_amd import sv
+    if precision == "fp32_valu":
+        return {}
+    prods = 1 if precision == "fp32_mfma" else 3
+    fused, _ = sv.sv_fuse(gates, n, sv.make_opts(max_k=max_k, fusion=fusion, precision=precision))
+    useful = issued = 0.0
+    for g in fused:
+        if g.k < 4:
+            continue
+        groups = 2.0 ** (n - g.k - len(g.controls))
+        useful += groups * 2 ** g.k * (8 * 2 ** g.k - 2)
+        issued += prods * 2.0 * 4.0 ** (g.k + 1) * groups
+    return {"mfma_useful_flops": useful, "mfma_issued_flops": issued, "products_per_pass": prods}
+
+
+def measured_ceilings(log) -> dict:
+    """Bandwidth a plain device copy and an in-place read-modify-write reach
+    on this GPU (torch's own kernels, 8 GiB tensors): the practical ceilings
+    next to the 8 TB/s vendor peak."""
+    import torch
+    a = torch.empty(1 << 30, dtype=torch.complex64, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    nbytes = a.numel() * a.element_size()
+    out = {}
+    for label, fn, moved in (("copy", lambda: b.copy_(a), 2 * nbytes), ("rmw_inplace_scale", lambda: a.mul_(1.0),
+                                                                          2 * nbytes)):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3 / 5
+        out[label + "_GBps"] = moved / t / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    log("ceilings:", out)
+    return out
+
+
+def grid30_rows(log) -> dict:
+    """The 30-qubit 5x6 depth-20 grid (845 gates): learned fusion in the
+    split and FP32 modes and greedy max-k = 6, GPU time and accuracy against
+    the oracle's stored full-state samples."""
+    import torch
+    from paper_2602_09604_amd import sv
+    n, gates, _ = workload("grid30")
+    garr = sv.GateArray(gates)
+    st = sv.State(n)
+    out = {}
+    try:
+        for fusion, K, prec in (("learned", 6, "fp16x3"), ("learned", 6, "fp32_mfma"), ("learned", 6, "fp32_valu"),
+                                ("greedy", 6, "fp16x3"), ("greedy", 4, "fp32_valu")):
+            best = None
+            for _ in range(2):
+                st.set_basis(0)
+                r = st.apply_circuit(garr, fusion=fusion, max_k=K, precision=prec, stats=True)
+                best = r if best is None or r["gpu_s"] < best["gpu_s"] else best
+            row = {"passes": best["passes"], "gpu_s": best["gpu_s"], "gates_per_s_gpu": len(gates) / best["gpu_s"],
+                   "alg_hbm_GBps": best["bytes"] / best["gpu_s"] / 1e9, "norm_drift": abs(st.norm() - 1.0)}
+            a = accuracy_vs_oracle(st, "grid30")
+            if a is not None:
+                row["accuracy_vs_oracle"] = a
+            out["%s%d_%s" % (fusion, K, prec)] = row
+            log("grid30 %s k=%d %s:" % (fusion, K, prec), row)
+    finally:
+        st.free()
+        del st
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_step(st, gates, opts_kw, sample):
     st.set_basis(0)
     stats = st.apply_circuit(gates, stats=True, **opts_kw)
@@ -114,6 +239,9 @@ def cpu_baseline(seconds_hint: float = 20.0) -> dict:
         "unit": "gates/s",
         "cores": oracle.threads(),
         "kind": "oracle",
+        "host": host_info(),
+        "why_not_34q": "a 34-qubit complex128 oracle state is 256 GiB; the sample runs at 26 qubits and is scaled "
+                       "(the oracle's cost is linear in 2^n)",
         "sample": "first %d gates of a 26-qubit 2x13 grid circuit (depth 24) in %.1f s = %.3g gates/s at 26 "
                   "qubits, scaled by 2^-8 to the 34-qubit state" % (count, dt, gps_n),
         "qft32_gates_per_s": len(qft) / qdt * 2.0 ** (qn - 32),
@@ -302,6 +430,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 512-circuit figures")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-others", action="store_true", help="skip the QFT / Grover / QV / state-read figures")
+    ap.add_argument("--no-precisions", action="store_true",
+                    help="skip the FP32 runs of the same circuit, the network-value runs and the 30-qubit rows")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-step", action="store_true",
                     help="counter-calibration copy + one untimed step, then exit (for rocprofv3 --pmc runs)")
@@ -415,6 +545,19 @@ def main():
                         for v in range(1, 5) if passes[v]},
         "dominant_avg_launch_ms": 1e3 * avg_launch,
     })
+    # the timed path's final state against the oracle's stored amplitudes
+    acc = accuracy_vs_oracle(st, args.workload)
+    if acc is not None:
+        acc["norm_drift"] = extra["norm_drift"]
+        extra["accuracy_vs_oracle"] = acc
+        log("accuracy vs oracle:", acc)
+    fl = issued_mfma_flops(gates, n, args.max_k, args.fusion, args.precision)
+    if fl:
+        mfma_s = agg["variant_s"][3] / args.steps
+        fl.update({"mfma_pass_s_per_step": mfma_s, "mfma_useful_TFLOPs": fl["mfma_useful_flops"] / mfma_s / 1e12,
+                   "mfma_issued_TFLOPs": fl["mfma_issued_flops"] / mfma_s / 1e12})
+        extra["mfma_flops_per_step"] = fl
+        log("mfma flops:", fl)
 
     if not args.no_greedy and args.fusion != "greedy":
         for mode in ("greedy", "block"):
@@ -423,7 +566,46 @@ def main():
             extra[mode + "_max_k"] = {"max_k": args.max_k, "gpu_s": g["gpu_s"], "passes": g["passes"],
                                       "fuse_s": g["fuse_s"], "gates_per_s_gpu": len(gates) / g["gpu_s"]}
             log("%s max_k=%d: %d passes %.3f s" % (mode, args.max_k, g["passes"], g["gpu_s"]))
-        extra["learned_over_greedy_gpu_time"] = agg["gpu_s"] / args.steps / extra["greedy_max_k"]["gpu_s"]
+        # the learned search (candidates, beams, blocks with controls, and the
+        # network) against first-come greedy blocks; network_value below
+        # separates what the network itself adds
+        extra["learned_search_over_greedy_gpu_time"] = agg["gpu_s"] / args.steps / extra["greedy_max_k"]["gpu_s"]
+    if not args.no_precisions and args.fusion == "learned":
+        # the paper's FP32 arithmetic on the same circuit and partition search,
+        # and what the trained network adds: the same search with the model
+        # removed keeps the fewest passes
+        import tempfile
+        tmp = tempfile.NamedTemporaryFile(suffix=".svcm", delete=False)
+        tmp.close()
+        sv.sv_cost_model_save(tmp.name)
+        rows = {}
+        try:
+            for prec in dict.fromkeys((args.precision, "fp32_mfma", "fp32_valu")):
+                for model in (True, False):
+                    if model:
+                        sv.sv_cost_model_load(tmp.name)
+                    else:
+                        sv.sv_cost_model_clear()
+                    if prec == "fp32_mfma" and not model:
+                        continue  # every matrix-core pass moves the same bytes: the FP16X3 pair shows the tie
+                    st.set_basis(0)
+                    r = st.apply_circuit(garr, fusion="learned", max_k=args.max_k, precision=prec, stats=True)
+                    row = {"passes": r["passes"], "gpu_s": r["gpu_s"], "gates_per_s_gpu": len(gates) / r["gpu_s"],
+                           "alg_hbm_GBps": r["bytes"] / r["gpu_s"] / 1e9, "norm_drift": abs(st.norm() - 1.0)}
+                    a = accuracy_vs_oracle(st, args.workload)
+                    if a is not None:
+                        row["accuracy_vs_oracle"] = a
+                    key = "%s_%s" % (prec, "model" if model else "no_model")
+                    rows[key] = row
+                    log("learned %s:" % key, row)
+        finally:
+            sv.sv_cost_model_load(tmp.name)
+            os.unlink(tmp.name)
+        extra["learned_by_precision"] = rows
+        extra["network_value"] = {
+            p_: {"model_over_no_model_gpu_time": rows[p_ + "_model"]["gpu_s"] / rows[p_ + "_no_model"]["gpu_s"],
+                 "passes_model": rows[p_ + "_model"]["passes"], "passes_no_model": rows[p_ + "_no_model"]["passes"]}
+            for p_ in dict.fromkeys((args.precision, "fp32_valu")) if p_ + "_no_model" in rows}
     if not args.no_plain:
         log("plain unfused FP32 run ...")
         st.set_basis(0)
@@ -432,11 +614,18 @@ def main():
             "gates_per_s_gpu": len(gates) / p["gpu_s"], "gpu_s": p["gpu_s"], "passes": p["passes"],
             "alg_hbm_GBps": p["bytes"] / p["gpu_s"] / 1e9, "norm": st.norm(),
         }
+        a = accuracy_vs_oracle(st, args.workload)
+        if a is not None:
+            extra["plain_fp32_unfused"]["accuracy_vs_oracle"] = a
         extra["speedup_vs_plain_fp32"] = gates_per_s / extra["plain_fp32_unfused"]["gates_per_s_gpu"]
         log("plain: %.3f s" % p["gpu_s"])
     st.free()
     del st
     torch.cuda.empty_cache()
+
+    if not args.no_precisions and args.workload == "grid34":
+        extra["grid30"] = grid30_rows(log)
+        extra["measured_ceilings"] = measured_ceilings(log)
 
     if not args.no_batch:
         log("batched 512-circuit workload ...")

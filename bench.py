@@ -311,6 +311,49 @@ def batch_figures(max_k: int) -> dict:
             s.free()
 
 
+def profile_workload(name: str, tune_qubits: int) -> None:
+    """One 32-qubit workload of other_workloads(), after the autotuner, run
+    twice (the second run is the one to read in a kernel trace).  It starts
+    with a copy of known size (8 GiB read, 8 GiB written) that calibrates
+    the HBM byte counters of rocprofv3 --pmc runs."""
+    import torch
+    import circuits as C
+    from paper_2602_09604_amd import sv
+    a = torch.empty(1 << 30, dtype=torch.complex64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    torch.cuda.empty_cache()
+    scratch = sv.State(tune_qubits)
+    sv.sv_autotune(scratch.h, 0)
+    scratch.free()
+    del scratch
+    torch.cuda.empty_cache()
+    n = 32
+    init = 0
+    if name.startswith("qft32"):
+        gates, init = C.qft_like_circuit(n), C.qft_input_basis(n, 0)
+        kw = dict(max_k=5, fusion=name.split("_")[1], precision="fp16x3")
+    elif name == "grover32":
+        gates = C.grover_circuit(n, 0x2D2D2D2D, 3)
+        kw = dict(max_k=6, fusion="greedy", precision="fp16x3")
+    else:
+        gates = C.quantum_volume_circuit(n, n, seed=0)
+        kw = dict(max_k=6, fusion=name.split("_")[1], precision="fp16x3")
+    st = sv.State(n)
+    try:
+        for rep in range(2):
+            st.set_basis(init)
+            s = st.apply_circuit(gates, stats=True, timing=True, **kw)
+            log("%s run %d: %d passes %.3f s, per family %s" % (name, rep, s["passes"], s["gpu_s"],
+                                                               {VARIANT_NAMES[v]: (s["variant_passes"][v],
+                                                                                   round(s["variant_s"][v], 4))
+                                                                for v in range(1, 5) if s["variant_passes"][v]}))
+    finally:
+        st.free()
+
+
 def other_workloads() -> dict:
     """The paper's other circuit families at 30-32 qubits and the state
     reads, each timed on the GPU (device time of the passes; wall time of
@@ -433,6 +476,9 @@ def main():
     ap.add_argument("--no-precisions", action="store_true",
                     help="skip the FP32 runs of the same circuit, the network-value runs and the 30-qubit rows")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--profile-workload", default=None,
+                    choices=["qft32_greedy", "qft32_phase", "grover32", "qv32_greedy", "qv32_learned"],
+                    help="autotune, then run one 32-qubit workload twice and exit (for rocprofv3 runs)")
     ap.add_argument("--profile-step", action="store_true",
                     help="counter-calibration copy + one untimed step, then exit (for rocprofv3 --pmc runs)")
     args = ap.parse_args()
@@ -444,6 +490,9 @@ def main():
     import torch
     from paper_2602_09604_amd import sv
 
+    if args.profile_workload:
+        profile_workload(args.profile_workload, args.tune_qubits)
+        return
     n, gates, desc = workload(args.workload)
     log("workload:", desc, "gates:", len(gates))
     if args.profile_step:

@@ -164,7 +164,7 @@ static std::vector<unsigned char> graph_key(const std::vector<Pass>& passes, con
   f.reserve(passes.size() * 28);
   for (const Pass& p : passes) {
     f.insert(f.end(), {p.k, p.variant, p.precision, (int64_t)p.mat_off, (int64_t)p.mat_bytes, p.tile_bits,
-                       p.reg_iters, p.mfma_cols, p.nhubs, (int64_t)p.cmask, (int64_t)p.cval, p.nmux});
+                       p.reg_iters, p.mfma_cols, p.nhubs, (int64_t)p.cmask, (int64_t)p.cval, p.nmux, p.mfma_x});
     f.insert(f.end(), p.s, p.s + SV_MAX_K);
     f.insert(f.end(), p.hub, p.hub + 8);
   }
@@ -197,6 +197,10 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
   std::vector<std::vector<float>> phase_data;    // phase passes: their tables
   size_t total = 0;
   auto add = [&](Pass& p) {
+    if (p.variant == V_MFMA) {
+      p.mfma_x = mfma_exchange_mask(s->n, p);
+      p.mat_bytes = pass_data_bytes(p);
+    }
     p.mat_off = total;
     total += align256(p.mat_bytes);
     passes.push_back(p);

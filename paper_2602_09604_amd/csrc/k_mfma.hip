@@ -276,6 +276,365 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
   mfma_body<K, PREC, LAYOUT, NT>(psi, Ag, a, lds4);
 }
 
+// ---- passes with targets on amplitude bits 1..3 -----------------------------
+//
+// A target on element bit t in {0, 1, 2} (amplitude bit t + 1) splits every
+// 128-byte line (8 elements) between the loads of different local indices:
+// a load instruction of the plain layout touches only half (or a quarter, or
+// an eighth) of each line, so such passes cannot stream non-temporally.  Here
+// the m low targets (set TM, m = popcount) are handled by a lane exchange:
+//
+//   * lane j (of 32) owns the group G(j) = u(j) | c(j) << (5 - m) of the
+//     tile, where c(j) are j's bits at the positions in TM and u(j) its
+//     other bits (both packed ascending);
+//   * load "slot" X of a unit reads, in lane j, the element of group
+//     u(j) | X << (5 - m) whose low-target local bits are c(j): the 8 lanes
+//     of an aligned octet then read the 8 elements of one whole line;
+//   * after the 2^m slots of a unit are loaded, a butterfly over the m
+//     targets (swaps with lane j ^ 2^t, t in TM) is the transpose that gives
+//     every lane the 2^m elements of its own group; stores undo it the same
+//     way (the transpose is its own inverse).
+//
+// A unit is 8 elements per lane covering element-local bits 0..2 (4 for the
+// k = 4 bit-0-target layout); the real matrix A' is encoded with its rows
+// and columns permuted so that each lane's k-rows (loads) and output rows
+// (stores) of one unit are exactly those 8 elements.
+
+template <int TM>
+struct LowBits {
+  static constexpr int m = (TM & 1) + ((TM >> 1) & 1) + ((TM >> 2) & 1);
+  static constexpr int t(int i) {
+    int c = 0;
+    for (int b = 0; b < 3; ++b)
+      if ((TM >> b) & 1) {
+        if (c == i) return b;
+        ++c;
+      }
+    return 0;
+  }
+};
+
+// value of the lane j ^ 2^T (T in 0..2; within aligned groups of 8 lanes)
+template <int T>
+__device__ __forceinline__ float lane_xor(float v) {
+  const int x = __float_as_int(v);
+  if constexpr (T == 0) return __int_as_float(__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true));  // quad_perm 1,0,3,2
+  else if constexpr (T == 1) return __int_as_float(__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true));  // 2,3,0,1
+  else return __int_as_float(__builtin_amdgcn_ds_swizzle(x, (4 << 10) | 0x1F));  // bit mode: xor 4
+}
+
+template <int TM, int I, int N>
+__device__ __forceinline__ void xstage(float4 (&R)[N], int j) {
+  constexpr int T = LowBits<TM>::t(I);
+  const bool hi = (j >> T) & 1;
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    if (r & (1 << I)) continue;
+    const int r1 = r | (1 << I);
+    // component-wise selects on values (a select between the two array
+    // elements themselves would take their addresses)
+    const float4 a0 = R[r], a1 = R[r1];
+    const float4 snd = make_float4(hi ? a0.x : a1.x, hi ? a0.y : a1.y, hi ? a0.z : a1.z, hi ? a0.w : a1.w);
+    const float4 rcv = make_float4(lane_xor<T>(snd.x), lane_xor<T>(snd.y), lane_xor<T>(snd.z), lane_xor<T>(snd.w));
+    R[r] = make_float4(hi ? rcv.x : a0.x, hi ? rcv.y : a0.y, hi ? rcv.z : a0.z, hi ? rcv.w : a0.w);
+    R[r1] = make_float4(hi ? a1.x : rcv.x, hi ? a1.y : rcv.y, hi ? a1.z : rcv.z, hi ? a1.w : rcv.w);
+  }
+}
+
+// register r of a unit: bits 0..m-1 the low-target local bits (before the
+// butterfly: the slot X), the rest the unit's other local bits
+template <int TM, int N>
+__device__ __forceinline__ void xtranspose(float4 (&R)[N], int j) {
+  constexpr int M = LowBits<TM>::m;
+  if constexpr (M >= 1) xstage<TM, 0, N>(R, j);
+  if constexpr (M >= 2) xstage<TM, 1, N>(R, j);
+  if constexpr (M >= 3) xstage<TM, 2, N>(R, j);
+}
+
+// bits of v at the positions of mask, packed ascending (5-bit values)
+__device__ __forceinline__ int compress5(int v, int mask) {
+  int o = 0, c = 0;
+#pragma unroll
+  for (int b = 0; b < 5; ++b)
+    if ((mask >> b) & 1) o |= ((v >> b) & 1) << c++;
+  return o;
+}
+
+// Unit geometry, shared by the kernel and the host encoding.
+//   PAIR split loads:  k-steps 2p, 2p+1; element e = 16p + 8h + 4 (s & 1) + q
+//   Q0 split loads:    k >= 5: k-steps 4p..4p+3, element t = 16p + 8h + 2 (s & 3) + q;
+//                      k = 4: t = 4h + 2s + q
+//   stores (every precision; output row i = 8q + 4h + 2w + ri of tile mt):
+//     PAIR: amplitude 16 mt + 8h + 2q + w;
+//     Q0:   amplitude 2t + w, t = 16 (mt >> 1) + 8h + 4 (mt & 1) + q (k >= 5), t = 4h + q (k = 4)
+//   FP32 loads keep the natural order (every lane loads every element).
+inline int x_pair_load_amp(int s, int h, int q) { return 16 * (s >> 1) + 8 * h + 4 * (s & 1) + q; }
+inline int x_q0_load_elem(int k, int s, int h, int q) {
+  return k >= 5 ? 16 * (s >> 2) + 8 * h + 2 * (s & 3) + q : 4 * h + 2 * s + q;
+}
+inline int x_store_amp(int layout, int k, int mt, int i) {
+  const int q = i >> 3, h = (i >> 2) & 1, w = (i >> 1) & 1;
+  if (layout == kLayoutPair) return 16 * mt + 8 * h + 2 * q + w;
+  const int t = k >= 5 ? 16 * (mt >> 1) + 8 * h + 4 * (mt & 1) + q : 4 * h + q;
+  return 2 * t + w;
+}
+
+template <int K, int PREC, int LAYOUT, int TM>
+__device__ __forceinline__ void mfma_body_x(float4* __restrict__ psi, const float4* __restrict__ Ag,
+                                            const MfmaArgs& a, float4* lds4) {
+  constexpr int DK = 1 << K;
+  constexpr int MT = (2 * DK) / 32;
+  constexpr bool SPLIT = PREC != SV_PREC_FP32_MFMA;
+  constexpr int KS = SPLIT ? (2 * DK) / 16 : DK;
+  constexpr int FRAG_BYTES = SPLIT ? MT * KS * 2 * 64 * 16 : MT * KS * 64 * 4;
+  constexpr int KQ = LAYOUT == kLayoutPair ? K : K - 1;
+  constexpr int COLS = LAYOUT == kLayoutPair ? 2 : 1;
+  constexpr int M = LowBits<TM>::m;
+  constexpr int XM = (1 << M) - 1;
+  constexpr bool Q0K4 = LAYOUT == kLayoutQ0 && K == 4;  // 4-element units
+  static_assert(!(Q0K4 && M > 2), "k = 4 with bit 0 as a target covers two low local bits per unit");
+  const int tid = threadIdx.x;
+  const unsigned v = blockIdx.x & ((1u << a.vbits) - 1);
+  const uint64_t wg = blockIdx.x >> a.vbits;
+  const uint64_t cb = a.cbits[v];
+  Ag += (size_t)v * (FRAG_BYTES / 16);
+  for (int i = tid; i < FRAG_BYTES / 16; i += 256) lds4[i] = Ag[i];
+  __syncthreads();
+  const int lane = tid & 63, h = lane >> 5, j = lane & 31;
+  const int uj = compress5(j, ~TM & 31), cj = compress5(j, TM);
+  // element offsets of the slots' group bits and of this lane's low-target bits
+  uint64_t xoff[XM + 1];
+#pragma unroll
+  for (int X = 0; X <= XM; ++X) {
+    uint64_t g = (uint64_t)X << (5 - M);
+#pragma unroll
+    for (int q = 0; q < KQ + kMfmaCtrl; ++q) g = ((g & ~a.ins[q]) << 1) | (g & a.ins[q]);
+    xoff[X] = g;
+  }
+  uint64_t offc = 0;
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+    if ((cj >> i) & 1) offc += a.stride[i];
+  uint64_t stride[KQ];  // local copy: the helpers below never take the kernel argument's address
+#pragma unroll
+  for (int i = 0; i < KQ; ++i) stride[i] = a.stride[i];
+  auto off = [&](int l) __attribute__((always_inline)) {
+    uint64_t o = 0;
+#pragma unroll
+    for (int i = 0; i < KQ; ++i)
+      if ((l >> i) & 1) o += stride[i];
+    return o;
+  };
+  // one unit: N registers; register r reads slot r & XM at local index
+  // ebase + (r & ~XM) (its low-target bits come from this lane's c)
+  auto load_unit = [&](auto& R, uint64_t b0, int ebase) __attribute__((always_inline)) {
+    constexpr int N = sizeof(R) / sizeof(R[0]);
+#pragma unroll
+    for (int r = 0; r < N; ++r) R[r] = gld<true>(psi + b0 + xoff[r & XM] + off(ebase + (r & ~XM)));
+    xtranspose<TM>(R, j);
+  };
+  auto store_unit = [&](auto& R, uint64_t b0, int ebase) __attribute__((always_inline)) {
+    constexpr int N = sizeof(R) / sizeof(R[0]);
+    xtranspose<TM>(R, j);
+#pragma unroll
+    for (int r = 0; r < N; ++r) gst<true>(psi + b0 + xoff[r & XM] + off(ebase + (r & ~XM)), R[r]);
+  };
+  const uint64_t wstride = (uint64_t)(gridDim.x >> a.vbits) * 4;
+  for (uint64_t wt = wg * 4 + (tid >> 6); wt < a.tiles; wt += wstride) {
+    const uint64_t b0 = mf_base<KQ>(wt * 32 + uj, cb, a) + offc;
+    // ---------------- B operand ----------------
+    using frag_t = typename std::conditional<PREC == SV_PREC_BF16X3, bf16x8, f16x8>::type;
+    float bf[COLS][SPLIT ? 1 : KS];
+    frag_t bhi[COLS][SPLIT ? KS : 1], blo[COLS][SPLIT ? KS : 1];
+    auto split = [&](int c, int s, const float (&x)[8]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        if constexpr (PREC == SV_PREC_BF16X3) {
+          const short hi = dev_bf16(x[e]);
+          bhi[c][s][e] = hi;
+          blo[c][s][e] = dev_bf16(x[e] - dev_bf16_f(hi));
+        } else {
+          const float xs = x[e] * kF16Scale;
+          const _Float16 hi = (_Float16)xs;
+          bhi[c][s][e] = hi;
+          blo[c][s][e] = (_Float16)((xs - (float)hi) * kF16LoScale);
+        }
+      }
+    };
+    if constexpr (!SPLIT) {
+      if constexpr (LAYOUT == kLayoutPair) {
+#pragma unroll
+        for (int p = 0; p < KS / 8; ++p) {
+          float4 R[8];
+          load_unit(R, b0, 8 * p);
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            bf[0][8 * p + r] = h ? R[r].y : R[r].x;
+            bf[1][8 * p + r] = h ? R[r].w : R[r].z;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int p = 0; p < KS / 16; ++p) {
+          float4 R[8];
+          load_unit(R, b0, 8 * p);
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            bf[0][2 * (8 * p + r)] = h ? R[r].y : R[r].x;
+            bf[0][2 * (8 * p + r) + 1] = h ? R[r].w : R[r].z;
+          }
+        }
+      }
+    } else if constexpr (LAYOUT == kLayoutPair) {
+#pragma unroll
+      for (int p = 0; p < KS / 2; ++p) {
+        float4 R[8];
+        load_unit(R, b0, 16 * p + 8 * h);
+#pragma unroll
+        for (int s1 = 0; s1 < 2; ++s1) {
+          float x0[8], x1[8];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float4 f = R[4 * s1 + q];
+            x0[2 * q] = f.x;
+            x0[2 * q + 1] = f.y;
+            x1[2 * q] = f.z;
+            x1[2 * q + 1] = f.w;
+          }
+          split(0, 2 * p + s1, x0);
+          split(1, 2 * p + s1, x1);
+        }
+      }
+    } else if constexpr (!Q0K4) {
+#pragma unroll
+      for (int p = 0; p < KS / 4; ++p) {
+        float4 R[8];
+        load_unit(R, b0, 16 * p + 8 * h);
+#pragma unroll
+        for (int s3 = 0; s3 < 4; ++s3) {
+          float x[8];
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const float4 f = R[2 * s3 + q];
+            x[4 * q] = f.x;
+            x[4 * q + 1] = f.y;
+            x[4 * q + 2] = f.z;
+            x[4 * q + 3] = f.w;
+          }
+          split(0, 4 * p + s3, x);
+        }
+      }
+    } else {
+      float4 R[4];
+      load_unit(R, b0, 4 * h);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        float x[8];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const float4 f = R[2 * s + q];
+          x[4 * q] = f.x;
+          x[4 * q + 1] = f.y;
+          x[4 * q + 2] = f.z;
+          x[4 * q + 3] = f.w;
+        }
+        split(0, s, x);
+      }
+    }
+    // ---------------- products of one 32-row output tile ----------------
+    auto tile = [&](int mt, f32x16 (&acc)[COLS]) __attribute__((always_inline)) {
+      if constexpr (!SPLIT) {
+        const float* A = reinterpret_cast<const float*>(lds4);
+#pragma unroll
+        for (int c = 0; c < COLS; ++c)
+#pragma unroll
+          for (int e = 0; e < 16; ++e) acc[c][e] = 0.f;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const float av = A[(mt * KS + s) * 64 + lane];
+#pragma unroll
+          for (int c = 0; c < COLS; ++c) acc[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bf[c][s], acc[c], 0, 0, 0);
+        }
+      } else {
+        const frag_t* A = reinterpret_cast<const frag_t*>(lds4);
+        f32x16 cor[COLS];
+#pragma unroll
+        for (int c = 0; c < COLS; ++c)
+#pragma unroll
+          for (int e = 0; e < 16; ++e) acc[c][e] = cor[c][e] = 0.f;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const frag_t ahi = A[((mt * KS + s) * 2 + 0) * 64 + lane];
+          const frag_t alo = A[((mt * KS + s) * 2 + 1) * 64 + lane];
+#pragma unroll
+          for (int c = 0; c < COLS; ++c) {
+            if constexpr (PREC == SV_PREC_BF16X3) {
+              acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi[c][s], acc[c], 0, 0, 0);
+              acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo[c][s], acc[c], 0, 0, 0);
+              acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi[c][s], acc[c], 0, 0, 0);
+            } else {
+              acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, bhi[c][s], acc[c], 0, 0, 0);
+              cor[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, blo[c][s], cor[c], 0, 0, 0);
+              cor[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(alo, bhi[c][s], cor[c], 0, 0, 0);
+            }
+          }
+        }
+        if constexpr (PREC == SV_PREC_FP16X3) {
+#pragma unroll
+          for (int c = 0; c < COLS; ++c)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[c][e] = (acc[c][e] + cor[c][e] * (1.f / kF16LoScale)) * (1.f / kF16Scale);
+        }
+      }
+    };
+    // ---------------- outputs ----------------
+    if constexpr (LAYOUT == kLayoutPair) {
+#pragma unroll 1
+      for (int mt = 0; mt < MT; ++mt) {
+        f32x16 acc[COLS];
+        tile(mt, acc);
+        float4 O[8];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int w = 0; w < 2; ++w)
+            O[2 * q + w] = make_float4(acc[0][4 * q + 2 * w], acc[0][4 * q + 2 * w + 1], acc[1][4 * q + 2 * w],
+                                       acc[1][4 * q + 2 * w + 1]);
+        store_unit(O, b0, 16 * mt + 8 * h);
+      }
+    } else if constexpr (!Q0K4) {
+#pragma unroll 1
+      for (int mp = 0; mp < MT / 2; ++mp) {
+        float4 O[8];
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+          f32x16 acc[COLS];
+          tile(2 * mp + w, acc);
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            O[4 * w + q] = make_float4(acc[0][4 * q], acc[0][4 * q + 1], acc[0][4 * q + 2], acc[0][4 * q + 3]);
+        }
+        store_unit(O, b0, 16 * mp + 8 * h);
+      }
+    } else {
+      f32x16 acc[COLS];
+      tile(0, acc);
+      float4 O[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        O[q] = make_float4(acc[0][4 * q], acc[0][4 * q + 1], acc[0][4 * q + 2], acc[0][4 * q + 3]);
+      store_unit(O, b0, 4 * h);
+    }
+  }
+}
+
+template <int K, int PREC, int LAYOUT, int TM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_apply_mfma_x(
+    float4* __restrict__ psi, const float4* __restrict__ Ag, const MfmaArgs a) {
+  extern __shared__ float4 lds4[];
+  mfma_body_x<K, PREC, LAYOUT, TM>(psi, Ag, a, lds4);
+}
+
 size_t frag_bytes(int k, int prec) {
   const int dk = 1 << k, mt = 2 * dk / 32;
   if (prec == SV_PREC_FP32_MFMA) return (size_t)mt * dk * 64 * 4;
@@ -320,7 +679,58 @@ void launch_k(int k, bool nt, const MfmaArgs& a, void* psi, const unsigned char*
   }
 }
 
+template <int K, int PREC, int LAYOUT, int TM>
+void launch_x_t(const MfmaArgs& a, void* psi, const unsigned char* data, hipStream_t st) {
+  const size_t lds = frag_bytes(K, PREC);
+  uint64_t per_value = (a.tiles + 3) / 4;
+  if (per_value > (8192u >> a.vbits)) per_value = 8192u >> a.vbits;
+  const uint64_t blocks = per_value << a.vbits;
+  hipLaunchKernelGGL((k_apply_mfma_x<K, PREC, LAYOUT, TM>), dim3((unsigned)blocks), dim3(256), lds, st,
+                     (float4*)psi, (const float4*)data, a);
+}
+
+template <int PREC, int LAYOUT, int TM>
+void launch_x_k(int k, const MfmaArgs& a, void* psi, const unsigned char* data, hipStream_t st) {
+  switch (k) {
+    case 4:
+      if constexpr (!(LAYOUT == kLayoutQ0 && LowBits<TM>::m > 2)) return launch_x_t<4, PREC, LAYOUT, TM>(a, psi, data, st);
+      break;
+    case 5: return launch_x_t<5, PREC, LAYOUT, TM>(a, psi, data, st);
+    case 6: return launch_x_t<6, PREC, LAYOUT, TM>(a, psi, data, st);
+    default: break;
+  }
+  throw DeviceError{hipErrorInvalidValue, "k_apply_mfma_x: unsupported k / low targets"};
+}
+
+template <int PREC, int LAYOUT>
+void launch_x(int tm, int k, const MfmaArgs& a, void* psi, const unsigned char* data, hipStream_t st) {
+  switch (tm) {
+    case 1: return launch_x_k<PREC, LAYOUT, 1>(k, a, psi, data, st);
+    case 2: return launch_x_k<PREC, LAYOUT, 2>(k, a, psi, data, st);
+    case 3: return launch_x_k<PREC, LAYOUT, 3>(k, a, psi, data, st);
+    case 4: return launch_x_k<PREC, LAYOUT, 4>(k, a, psi, data, st);
+    case 5: return launch_x_k<PREC, LAYOUT, 5>(k, a, psi, data, st);
+    case 6: return launch_x_k<PREC, LAYOUT, 6>(k, a, psi, data, st);
+    case 7: return launch_x_k<PREC, LAYOUT, 7>(k, a, psi, data, st);
+    default: throw DeviceError{hipErrorInvalidValue, "k_apply_mfma_x: low-target mask"};
+  }
+}
+
 }  // namespace
+
+// Low-target mask of the lane-exchange form (0: the plain kernel).  Used for
+// streamed states when a target (other than bit 0) sits on amplitude bits
+// 1..3 and no control does; a bit-0-target pass with k = 4 covers only two
+// low local bits per unit.
+int mfma_exchange_mask(int n, const Pass& p) {
+  if (n < kern::kNtMinQubits || (p.cmask & 0xEull)) return 0;
+  const bool q0 = p.s[0] == 0;
+  int tm = 0;
+  for (int j = q0 ? 1 : 0; j < p.k; ++j)
+    if (p.s[j] >= 1 && p.s[j] <= 3) tm |= 1 << (p.s[j] - 1);
+  if (q0 && p.k == 4 && __builtin_popcount(tm) > 2) return 0;
+  return tm;
+}
 
 bool mfma_supported(int k, int precision) {
   return k >= 4 && k <= 6 &&
@@ -334,13 +744,24 @@ size_t mfma_data_bytes(const Pass& p) { return frag_bytes(p.k, p.precision) * (p
 // holding A'[32 mt + i][16 s + 8 h + e]; part 0 = hi, part 1 = lo.
 void mfma_encode(const Pass& p, const double* mat, unsigned char* dst) {
   const int dk = 1 << p.k, mt_n = 2 * dk / 32;
+  // With the lane exchange (p.mfma_x) the rows and the split modes' columns
+  // of A' are permuted to the unit geometry of the exchange kernel.
+  const int layout = p.s[0] == 0 ? kLayoutQ0 : kLayoutPair;
+  auto row_of = [&](int mt, int i) {
+    return p.mfma_x ? 2 * x_store_amp(layout, p.k, mt, i) + (i & 1) : 32 * mt + i;
+  };
+  auto split_col_of = [&](int s, int h, int e) {
+    if (!p.mfma_x) return 16 * s + 8 * h + e;
+    if (layout == kLayoutPair) return 2 * x_pair_load_amp(s, h, e >> 1) + (e & 1);
+    return 2 * (2 * x_q0_load_elem(p.k, s, h, e >> 2) + ((e >> 1) & 1)) + (e & 1);
+  };
   if (p.precision == SV_PREC_FP32_MFMA) {
     float* f = reinterpret_cast<float*>(dst);
     for (int mt = 0; mt < mt_n; ++mt)
       for (int s = 0; s < dk; ++s)
         for (int lane = 0; lane < 64; ++lane) {
           const int h = lane >> 5, i = lane & 31;
-          f[(mt * dk + s) * 64 + lane] = (float)a4m(mat, dk, 32 * mt + i, 2 * s + h);
+          f[(mt * dk + s) * 64 + lane] = (float)a4m(mat, dk, row_of(mt, i), 2 * s + h);
         }
     return;
   }
@@ -351,7 +772,7 @@ void mfma_encode(const Pass& p, const double* mat, unsigned char* dst) {
       for (int lane = 0; lane < 64; ++lane)
         for (int e = 0; e < 8; ++e) {
           const int h = lane >> 5, i = lane & 31;
-          const double v = a4m(mat, dk, 32 * mt + i, 16 * s + 8 * h + e);
+          const double v = a4m(mat, dk, row_of(mt, i), split_col_of(s, h, e));
           uint16_t hi, lo;
           if (p.precision == SV_PREC_BF16X3) {
             hi = host_bf16((float)v);
@@ -417,6 +838,22 @@ void launch_mfma(const Pass& p, int n, void* psi, const unsigned char* data, hip
   for (int j = 0; j < SV_MAX_K + kMfmaCtrl; ++j) a.ins[j] = j < m ? ((uint64_t)1 << ins[j]) - 1 : ~(uint64_t)0;
   if (a.tiles == 0) throw DeviceError{hipErrorInvalidValue, "k_apply_mfma: state too small for a 32-group tile"};
   const bool pair = layout == kLayoutPair;
+  if (p.mfma_x) {
+    if (p.mfma_x != mfma_exchange_mask(n, p)) throw DeviceError{hipErrorInvalidValue, "k_apply_mfma: stale exchange mask"};
+    switch (p.precision) {
+      case SV_PREC_FP32_MFMA:
+        return pair ? launch_x<SV_PREC_FP32_MFMA, kLayoutPair>(p.mfma_x, p.k, a, psi, data, st)
+                    : launch_x<SV_PREC_FP32_MFMA, kLayoutQ0>(p.mfma_x, p.k, a, psi, data, st);
+      case SV_PREC_BF16X3:
+        return pair ? launch_x<SV_PREC_BF16X3, kLayoutPair>(p.mfma_x, p.k, a, psi, data, st)
+                    : launch_x<SV_PREC_BF16X3, kLayoutQ0>(p.mfma_x, p.k, a, psi, data, st);
+      case SV_PREC_FP16X3:
+        return pair ? launch_x<SV_PREC_FP16X3, kLayoutPair>(p.mfma_x, p.k, a, psi, data, st)
+                    : launch_x<SV_PREC_FP16X3, kLayoutQ0>(p.mfma_x, p.k, a, psi, data, st);
+      default:
+        throw DeviceError{hipErrorInvalidValue, "k_apply_mfma: precision"};
+    }
+  }
   // streaming stores only when no target or control leaves partial lines
   bool nt = kern::gather_nt(n, p.k, p.s);
   if (p.cmask & 0xEull) nt = false;

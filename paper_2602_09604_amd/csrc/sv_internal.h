@@ -73,6 +73,10 @@ struct Pass {
   // value of the c control bits in cmask (value v: control t = bit t of v),
   // their data one after another; cval is unused
   int nmux = 0;
+  // matrix cores on a streamed state with targets on amplitude bits 1..3:
+  // the bits (t - 1) of those targets, for the lane-exchange kernel and its
+  // permuted encoding (0: the plain kernel); set by mfma_exchange_mask
+  int mfma_x = 0;
 };
 
 // Launch shape defaults / tuned values.
@@ -97,6 +101,7 @@ void launch_norm_noalloc(const void* psi, int n, double* out, hipStream_t st);
 size_t pass_data_bytes(const Pass& p);
 void encode_pass_data(const Pass& p, const double* mat, unsigned char* dst);
 bool mfma_supported(int k, int precision);
+int mfma_exchange_mask(int n, const Pass& p);
 // Controls the matrix-core kernel takes: at most three, none on bit 0, and at
 // least one 32-group tile left.
 bool mfma_ctrl_supported(int n, int k, uint64_t cmask);

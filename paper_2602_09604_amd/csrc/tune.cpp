@@ -137,6 +137,7 @@ int sv_autotune(sv_state* s, int budget_ms) {
             for (auto& cand : cands) {
               p.variant = cand.first;
               p.tile_bits = cand.second;
+              p.mfma_x = p.variant == V_MFMA ? mfma_exchange_mask(n, p) : 0;
               p.mat_bytes = pass_data_bytes(p);
               p.mat_off = 0;
               encode_pass_data(p, mat.data(), host);

@@ -56,12 +56,8 @@ float host_bf16_to_f(uint16_t h) {
   return f;
 }
 
-// ---- device-side conversions ----------------------------------------------
-__device__ __forceinline__ short dev_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (short)(u >> 16);
-}
+// ---- device-side conversions (gfx950 converts to bf16 natively, RNE) -------
+__device__ __forceinline__ short dev_bf16(float f) { return __builtin_bit_cast(short, (__bf16)f); }
 __device__ __forceinline__ float dev_bf16_f(short h) { return __uint_as_float((uint32_t)(uint16_t)h << 16); }
 
 // Controls of a controlled pass: the pass covers only the groups whose
@@ -96,20 +92,14 @@ __device__ __forceinline__ uint64_t mf_off(int l, const MfmaArgs& a) {
   return o;
 }
 
-// Register policy: with every output tile unrolled the compiler keeps all
-// accumulators and A fragments live.  That fits two waves per SIMD for the
-// BF16/FP32 PAIR layout; the Q0 layout and FP16 (two accumulator sets) keep
-// the output-tile loop rolled and ask for two waves per SIMD instead.
-template <int PREC, int LAYOUT>
-struct MfmaPolicy {
-  static constexpr bool rolled = LAYOUT == kLayoutQ0 || PREC == SV_PREC_FP16X3;
-};
-
-// PREC: SV_PREC_FP32_MFMA, SV_PREC_BF16X3 or SV_PREC_FP16X3.
+// PREC: SV_PREC_FP32_MFMA, SV_PREC_BF16X3 or SV_PREC_FP16X3.  The output
+// tiles are computed one at a time (loop not unrolled) with two waves per
+// SIMD: unrolled, the compiler kept every tile's accumulators live and the
+// streaming k = 6 forms needed all 256 VGPRs (one wave per SIMD, measured
+// 1.5-2x slower for FP32 and BF16).
 template <int K, int PREC, int LAYOUT, bool NT>
 __device__ __forceinline__ void mfma_body(float4* __restrict__ psi, const float4* __restrict__ Ag, const MfmaArgs& a,
                                           float4* lds4) {
-  constexpr int MT_UNROLL = MfmaPolicy<PREC, LAYOUT>::rolled ? 1 : (2 << K) / 32;
   constexpr int DK = 1 << K;                 // amplitudes per group
   constexpr int MT = (2 * DK) / 32;          // 32-row output tiles
   constexpr bool SPLIT = PREC != SV_PREC_FP32_MFMA;
@@ -149,7 +139,7 @@ __device__ __forceinline__ void mfma_body(float4* __restrict__ psi, const float4
         }
       }
       const float* A = reinterpret_cast<const float*>(lds4);
-#pragma unroll MT_UNROLL
+#pragma unroll 1
       for (int mt = 0; mt < MT; ++mt) {
         f32x16 acc[COLS];
 #pragma unroll
@@ -217,7 +207,7 @@ __device__ __forceinline__ void mfma_body(float4* __restrict__ psi, const float4
           }
       }
       const frag_t* A = reinterpret_cast<const frag_t*>(lds4);
-#pragma unroll MT_UNROLL
+#pragma unroll 1
       for (int mt = 0; mt < MT; ++mt) {
         f32x16 acc[COLS], cor[COLS];
 #pragma unroll
@@ -260,13 +250,6 @@ __device__ __forceinline__ void mfma_body(float4* __restrict__ psi, const float4
       }
     }
   }
-}
-
-template <int K, int PREC, int LAYOUT, bool NT>
-__global__ __launch_bounds__(256) void k_apply_mfma(float4* __restrict__ psi, const float4* __restrict__ Ag,
-                                                    const MfmaArgs a) {
-  extern __shared__ float4 lds4[];
-  mfma_body<K, PREC, LAYOUT, NT>(psi, Ag, a, lds4);
 }
 
 template <int K, int PREC, int LAYOUT, bool NT>
@@ -658,12 +641,8 @@ void launch_t(const MfmaArgs& a, void* psi, const unsigned char* data, hipStream
   uint64_t per_value = (a.tiles + 3) / 4;
   if (per_value > (8192u >> a.vbits)) per_value = 8192u >> a.vbits;
   const uint64_t blocks = per_value << a.vbits;
-  if constexpr (MfmaPolicy<PREC, LAYOUT>::rolled)
-    hipLaunchKernelGGL((k_apply_mfma_rolled<K, PREC, LAYOUT, NT>), dim3((unsigned)blocks), dim3(256), lds, st,
-                       (float4*)psi, (const float4*)data, a);
-  else
-    hipLaunchKernelGGL((k_apply_mfma<K, PREC, LAYOUT, NT>), dim3((unsigned)blocks), dim3(256), lds, st, (float4*)psi,
-                       (const float4*)data, a);
+  hipLaunchKernelGGL((k_apply_mfma_rolled<K, PREC, LAYOUT, NT>), dim3((unsigned)blocks), dim3(256), lds, st,
+                     (float4*)psi, (const float4*)data, a);
 }
 
 template <int PREC, int LAYOUT>

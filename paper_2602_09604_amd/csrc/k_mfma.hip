@@ -618,6 +618,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
   mfma_body_x<K, PREC, LAYOUT, TM>(psi, Ag, a, lds4);
 }
 
+constexpr uint64_t kMfmaGroups = 65536;  // workgroup cap of a matrix-core launch
+
 size_t frag_bytes(int k, int prec) {
   const int dk = 1 << k, mt = 2 * dk / 32;
   if (prec == SV_PREC_FP32_MFMA) return (size_t)mt * dk * 64 * 4;
@@ -635,11 +637,12 @@ inline double a4m(const double* mat, int dk, int row, int col) {
 template <int K, int PREC, int LAYOUT, bool NT>
 void launch_t(const MfmaArgs& a, void* psi, const unsigned char* data, hipStream_t st) {
   const size_t lds = frag_bytes(K, PREC);
-  // 8192 workgroups (32 per CU, four times what can be resident at once):
-  // measured faster than one resident round or than one tile per wave.
-  // They are shared out evenly over the control values.
+  // Up to 65536 workgroups (256 per CU; 512 are resident at a time), shared
+  // out evenly over the control values.  Swept at 30, 32 and 34 qubits over
+  // 2048..262144: 65536 is the best or within noise of it for every target
+  // set, 2-5 % ahead of 8192 (which gave each wave 8x more tiles at 34 qubits).
   uint64_t per_value = (a.tiles + 3) / 4;
-  if (per_value > (8192u >> a.vbits)) per_value = 8192u >> a.vbits;
+  if (per_value > (kMfmaGroups >> a.vbits)) per_value = kMfmaGroups >> a.vbits;
   const uint64_t blocks = per_value << a.vbits;
   hipLaunchKernelGGL((k_apply_mfma_rolled<K, PREC, LAYOUT, NT>), dim3((unsigned)blocks), dim3(256), lds, st,
                      (float4*)psi, (const float4*)data, a);
@@ -662,7 +665,7 @@ template <int K, int PREC, int LAYOUT, int TM>
 void launch_x_t(const MfmaArgs& a, void* psi, const unsigned char* data, hipStream_t st) {
   const size_t lds = frag_bytes(K, PREC);
   uint64_t per_value = (a.tiles + 3) / 4;
-  if (per_value > (8192u >> a.vbits)) per_value = 8192u >> a.vbits;
+  if (per_value > (kMfmaGroups >> a.vbits)) per_value = kMfmaGroups >> a.vbits;
   const uint64_t blocks = per_value << a.vbits;
   hipLaunchKernelGGL((k_apply_mfma_x<K, PREC, LAYOUT, TM>), dim3((unsigned)blocks), dim3(256), lds, st,
                      (float4*)psi, (const float4*)data, a);

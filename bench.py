@@ -312,7 +312,8 @@ def batch_figures(max_k: int) -> dict:
 
 
 def profile_workload(name: str, tune_qubits: int) -> None:
-    """One 32-qubit workload of other_workloads(), after the autotuner, run
+    """One 32-qubit workload of other_workloads() (or the 30-qubit grid at a
+    small greedy max k, whose passes are all k <= 3), after the autotuner, run
     twice (the second run is the one to read in a kernel trace).  It starts
     with a copy of known size (8 GiB read, 8 GiB written) that calibrates
     the HBM byte counters of rocprofv3 --pmc runs."""
@@ -332,7 +333,11 @@ def profile_workload(name: str, tune_qubits: int) -> None:
     torch.cuda.empty_cache()
     n = 32
     init = 0
-    if name.startswith("qft32"):
+    if name.startswith("grid30"):
+        n = 30
+        gates = C.grid_circuit(5, 6, 20, seed=0)
+        kw = dict(max_k=int(name[-1]), fusion="greedy", precision="fp32_valu")
+    elif name.startswith("qft32"):
         gates, init = C.qft_like_circuit(n), C.qft_input_basis(n, 0)
         kw = dict(max_k=5, fusion=name.split("_")[1], precision="fp16x3")
     elif name == "grover32":
@@ -477,8 +482,9 @@ def main():
                     help="skip the FP32 runs of the same circuit, the network-value runs and the 30-qubit rows")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-workload", default=None,
-                    choices=["qft32_greedy", "qft32_phase", "grover32", "qv32_greedy", "qv32_learned"],
-                    help="autotune, then run one 32-qubit workload twice and exit (for rocprofv3 runs)")
+                    choices=["qft32_greedy", "qft32_phase", "grover32", "qv32_greedy", "qv32_learned",
+                             "grid30_greedy2", "grid30_greedy3"],
+                    help="autotune, then run one 30/32-qubit workload twice and exit (for rocprofv3 runs)")
     ap.add_argument("--profile-step", action="store_true",
                     help="counter-calibration copy + one untimed step, then exit (for rocprofv3 --pmc runs)")
     args = ap.parse_args()

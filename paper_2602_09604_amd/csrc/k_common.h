@@ -86,6 +86,77 @@ inline bool gather_nt(int n, int k, const int* s) {
   return true;
 }
 
+// ---- lane exchange for targets on amplitude bits 1..3 ----------------------
+// A target on element bit t in {0, 1, 2} (16-byte elements; amplitude bit
+// t + 1) splits every 128-byte line between the loads of different local
+// indices.  The exchange forms let 8 aligned lanes read one whole line per
+// load (each lane the element of another group whose low-target bits are the
+// lane's own bits there) and then transpose the loaded elements across those
+// lanes with a butterfly of lane swaps, so that every lane holds its own
+// group; stores undo it.  TM is the set of such target bits (element bits),
+// m = popcount(TM); register r of a unit has the low-target local bits in
+// its bits 0..m-1.
+template <int TM>
+struct LowBits {
+  static constexpr int m = (TM & 1) + ((TM >> 1) & 1) + ((TM >> 2) & 1);
+  static constexpr int t(int i) {
+    int c = 0;
+    for (int b = 0; b < 3; ++b)
+      if ((TM >> b) & 1) {
+        if (c == i) return b;
+        ++c;
+      }
+    return 0;
+  }
+};
+
+// value of the lane j ^ 2^T (T in 0..2; within aligned groups of 8 lanes)
+template <int T>
+__device__ __forceinline__ float lane_xor(float v) {
+  const int x = __float_as_int(v);
+  if constexpr (T == 0) return __int_as_float(__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true));  // quad_perm 1,0,3,2
+  else if constexpr (T == 1) return __int_as_float(__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true));  // 2,3,0,1
+  else return __int_as_float(__builtin_amdgcn_ds_swizzle(x, (4 << 10) | 0x1F));  // bit mode: xor 4
+}
+
+template <int TM, int I, int N>
+__device__ __forceinline__ void xstage(float4 (&R)[N], int j) {
+  constexpr int T = LowBits<TM>::t(I);
+  const bool hi = (j >> T) & 1;
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    if (r & (1 << I)) continue;
+    const int r1 = r | (1 << I);
+    // component-wise selects on values (a select between the two array
+    // elements themselves would take their addresses)
+    const float4 a0 = R[r], a1 = R[r1];
+    const float4 snd = make_float4(hi ? a0.x : a1.x, hi ? a0.y : a1.y, hi ? a0.z : a1.z, hi ? a0.w : a1.w);
+    const float4 rcv = make_float4(lane_xor<T>(snd.x), lane_xor<T>(snd.y), lane_xor<T>(snd.z), lane_xor<T>(snd.w));
+    R[r] = make_float4(hi ? rcv.x : a0.x, hi ? rcv.y : a0.y, hi ? rcv.z : a0.z, hi ? rcv.w : a0.w);
+    R[r1] = make_float4(hi ? a1.x : rcv.x, hi ? a1.y : rcv.y, hi ? a1.z : rcv.z, hi ? a1.w : rcv.w);
+  }
+}
+
+// register r of a unit: bits 0..m-1 the low-target local bits (before the
+// butterfly: the slot X), the rest the unit's other local bits
+template <int TM, int N>
+__device__ __forceinline__ void xtranspose(float4 (&R)[N], int j) {
+  constexpr int M = LowBits<TM>::m;
+  if constexpr (M >= 1) xstage<TM, 0, N>(R, j);
+  if constexpr (M >= 2) xstage<TM, 1, N>(R, j);
+  if constexpr (M >= 3) xstage<TM, 2, N>(R, j);
+}
+
+// bits of v at the positions of mask (BITS-bit values), packed ascending
+template <int BITS>
+__device__ __forceinline__ int compress_bits(int v, int mask) {
+  int o = 0, c = 0;
+#pragma unroll
+  for (int b = 0; b < BITS; ++b)
+    if ((mask >> b) & 1) o |= ((v >> b) & 1) << c++;
+  return o;
+}
+
 __device__ __forceinline__ void cmac(float2& acc, const float2 u, const float2 v) {
   acc.x = fmaf(u.x, v.x, acc.x);
   acc.x = fmaf(-u.y, v.y, acc.x);

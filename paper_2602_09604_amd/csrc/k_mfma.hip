@@ -32,6 +32,9 @@ namespace sv {
 namespace {
 using kern::gld;
 using kern::gst;
+using kern::compress_bits;
+using kern::LowBits;
+using kern::xtranspose;
 
 typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8;
 typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
@@ -283,66 +286,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 // and columns permuted so that each lane's k-rows (loads) and output rows
 // (stores) of one unit are exactly those 8 elements.
 
-template <int TM>
-struct LowBits {
-  static constexpr int m = (TM & 1) + ((TM >> 1) & 1) + ((TM >> 2) & 1);
-  static constexpr int t(int i) {
-    int c = 0;
-    for (int b = 0; b < 3; ++b)
-      if ((TM >> b) & 1) {
-        if (c == i) return b;
-        ++c;
-      }
-    return 0;
-  }
-};
-
-// value of the lane j ^ 2^T (T in 0..2; within aligned groups of 8 lanes)
-template <int T>
-__device__ __forceinline__ float lane_xor(float v) {
-  const int x = __float_as_int(v);
-  if constexpr (T == 0) return __int_as_float(__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true));  // quad_perm 1,0,3,2
-  else if constexpr (T == 1) return __int_as_float(__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true));  // 2,3,0,1
-  else return __int_as_float(__builtin_amdgcn_ds_swizzle(x, (4 << 10) | 0x1F));  // bit mode: xor 4
-}
-
-template <int TM, int I, int N>
-__device__ __forceinline__ void xstage(float4 (&R)[N], int j) {
-  constexpr int T = LowBits<TM>::t(I);
-  const bool hi = (j >> T) & 1;
-#pragma unroll
-  for (int r = 0; r < N; ++r) {
-    if (r & (1 << I)) continue;
-    const int r1 = r | (1 << I);
-    // component-wise selects on values (a select between the two array
-    // elements themselves would take their addresses)
-    const float4 a0 = R[r], a1 = R[r1];
-    const float4 snd = make_float4(hi ? a0.x : a1.x, hi ? a0.y : a1.y, hi ? a0.z : a1.z, hi ? a0.w : a1.w);
-    const float4 rcv = make_float4(lane_xor<T>(snd.x), lane_xor<T>(snd.y), lane_xor<T>(snd.z), lane_xor<T>(snd.w));
-    R[r] = make_float4(hi ? rcv.x : a0.x, hi ? rcv.y : a0.y, hi ? rcv.z : a0.z, hi ? rcv.w : a0.w);
-    R[r1] = make_float4(hi ? a1.x : rcv.x, hi ? a1.y : rcv.y, hi ? a1.z : rcv.z, hi ? a1.w : rcv.w);
-  }
-}
-
-// register r of a unit: bits 0..m-1 the low-target local bits (before the
-// butterfly: the slot X), the rest the unit's other local bits
-template <int TM, int N>
-__device__ __forceinline__ void xtranspose(float4 (&R)[N], int j) {
-  constexpr int M = LowBits<TM>::m;
-  if constexpr (M >= 1) xstage<TM, 0, N>(R, j);
-  if constexpr (M >= 2) xstage<TM, 1, N>(R, j);
-  if constexpr (M >= 3) xstage<TM, 2, N>(R, j);
-}
-
-// bits of v at the positions of mask, packed ascending (5-bit values)
-__device__ __forceinline__ int compress5(int v, int mask) {
-  int o = 0, c = 0;
-#pragma unroll
-  for (int b = 0; b < 5; ++b)
-    if ((mask >> b) & 1) o |= ((v >> b) & 1) << c++;
-  return o;
-}
-
 // Unit geometry, shared by the kernel and the host encoding.
 //   PAIR split loads:  k-steps 2p, 2p+1; element e = 16p + 8h + 4 (s & 1) + q
 //   Q0 split loads:    k >= 5: k-steps 4p..4p+3, element t = 16p + 8h + 2 (s & 3) + q;
@@ -384,7 +327,7 @@ __device__ __forceinline__ void mfma_body_x(float4* __restrict__ psi, const floa
   for (int i = tid; i < FRAG_BYTES / 16; i += 256) lds4[i] = Ag[i];
   __syncthreads();
   const int lane = tid & 63, h = lane >> 5, j = lane & 31;
-  const int uj = compress5(j, ~TM & 31), cj = compress5(j, TM);
+  const int uj = compress_bits<5>(j, ~TM & 31), cj = compress_bits<5>(j, TM);
   // element offsets of the slots' group bits and of this lane's low-target bits
   uint64_t xoff[XM + 1];
 #pragma unroll

@@ -82,10 +82,15 @@ int choose_variant(int n, int k, const int* s, int precision, int requested) {
   if (tv == V_MFMA && mfma_ok) return V_MFMA;
   if (tv == V_LDS && lds_feasible(n, k, s, sh.tile_bits)) return V_LDS;
   if (tv == V_REG) return V_REG;
-  // untuned defaults, from sweeps at 30 qubits: matrix cores for k >= 4 when
-  // the precision asks for them; LDS staging for low targets up to k = 4
+  // untuned defaults, from sweeps at 30 and 32 qubits: matrix cores for k >= 4
+  // when the precision asks for them; the wavefront shuffle for k <= 2 with
+  // every target in bits 0..6; on streamed states the register kernel
+  // whenever it reads whole lines (its lane exchange covers targets on bits
+  // 1..3): 0.68-0.76 of peak against 0.49-0.65 for LDS staging on every
+  // low-target set measured; LDS staging for other low targets up to k = 4
   if (precision != SV_PREC_FP32_VALU && mfma_ok) return V_MFMA;
   if (shfl_ok && k <= 2) return V_SHFL;  // at k = 3 the permutes cost more; only when tuned
+  if (reg_streams(n, k, s)) return V_REG;
   if (has_low_target(k, s) && k <= 4 && lds_feasible(n, k, s, sh.tile_bits)) return V_LDS;
   return V_REG;
 }

@@ -102,6 +102,10 @@ size_t pass_data_bytes(const Pass& p);
 void encode_pass_data(const Pass& p, const double* mat, unsigned char* dst);
 bool mfma_supported(int k, int precision);
 int mfma_exchange_mask(int n, const Pass& p);
+// The register kernel streams a pass non-temporally with whole-line accesses:
+// no target on amplitude bits 1..3, or at most three element-space targets
+// with the lane exchange (k_apply_reg.hip).
+bool reg_streams(int n, int k, const int* s);
 // Controls the matrix-core kernel takes: at most three, none on bit 0, and at
 // least one 32-group tile left.
 bool mfma_ctrl_supported(int n, int k, uint64_t cmask);

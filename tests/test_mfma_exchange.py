@@ -1,9 +1,10 @@
-"""Matrix-core passes with targets on amplitude bits 1..3 on streamed states
-(26 qubits and more), where the lane-exchange kernel runs: every low-target
-set (bits 1, 2, 3 alone, in pairs, all three), with and without bit 0 as a
-target, k = 4..6, FP32 / BF16 / FP16 matrix cores, plus controlled passes
-(one control value, and all values of a block in one launch), each against
-the oracle applying the same gate (Eq. 4) to the same random state."""
+"""Passes with targets on amplitude bits 1..3 on streamed states (26 qubits
+and more), where the lane-exchange kernels run: every low-target set (bits
+1, 2, 3 alone, in pairs, all three), with and without bit 0 as a target --
+matrix cores for k = 4..6 in FP32 / BF16 / FP16 plus controlled passes (one
+control value, and all values of a block in one launch), and the FP32
+register kernel for k = 1..3 (k = 4 with bit 0) -- each against the oracle
+applying the same gate (Eq. 4) to the same random state."""
 import sys
 
 import numpy as np
@@ -51,9 +52,9 @@ def targets_for(tm, k, q0, rng):
     return tuple(qs)
 
 
-def run_and_check(st, psi0, ref0, gates, prec):
+def run_and_check(st, psi0, ref0, gates, prec, variant="mfma"):
     st.write(0, psi0)
-    st.apply_circuit(gates, fusion="none", precision=prec, variant="mfma")
+    st.apply_circuit(gates, fusion="none", precision=prec, variant=variant)
     got = st.read()
     ref = ref0.copy()
     for g in gates:
@@ -92,3 +93,18 @@ def test_low_targets_with_controls(setup, prec):
             r = run_and_check(st, psi0, ref0, gates, prec)
             say(prec, "targets", qs, "controls", ctl, "gates", len(gates), r)
             assert r["max_abs"] <= MAX_ABS and r["infidelity"] <= INFID, (qs, ctl, r)
+
+
+@pytest.mark.parametrize("k,q0", [(1, False), (2, False), (3, False), (2, True), (3, True), (4, True)])
+def test_register_low_target_sets(setup, k, q0):
+    st, psi0, ref0 = setup
+    rng = np.random.Generator(np.random.PCG64(50 + k * 10 + q0))
+    kq = k - 1 if q0 else k  # targets that are not bit 0
+    for tm in range(1, 8):
+        if bin(tm).count("1") > kq:
+            continue
+        qs = targets_for(tm, k, q0, rng)
+        g = C.Gate(qs, C.haar_unitary(k, rng))
+        r = run_and_check(st, psi0, ref0, [g], "fp32_valu", variant="reg")
+        say("reg k=%d" % k, "targets", qs, r)
+        assert r["max_abs"] <= MAX_ABS and r["infidelity"] <= INFID, (qs, r)

@@ -296,8 +296,12 @@ def batch_figures(max_k: int) -> dict:
         wall_seq = time.perf_counter() - t0
         gpu_seq = e0.elapsed_time(e1) * 1e-3
         amps = sum(1 << n for n in ns)
+        floor = sum(16 << n for n in ns)  # every state read once and written once
         return {
             "circuits": 512, "gates": int(st["gates_in"]), "passes": int(st["passes"]),
+            "launches_in_graph": int(st["launches"]),
+            "alg_hbm_bytes": int(st["bytes"]), "hbm_floor_bytes": floor,
+            "alg_bytes_over_floor": st["bytes"] / floor,
             "batched_gpu_s": st["gpu_s"], "batched_wall_s": wall_batch, "batched_fuse_s": st["fuse_s"],
             "batched_circuits_per_s_gpu": 512 / st["gpu_s"],
             "batched_circuits_per_s_wall": 512 / wall_batch,

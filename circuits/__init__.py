@@ -31,7 +31,7 @@ __all__ = [
     "batched_ansatz", "ansatz_circuit", "mirror_circuit", "random_circuit",
     "grover_circuit", "quantum_volume_circuit", "synthetic_fusion_circuit",
     "to_arrays", "from_arrays", "save_npz", "load_npz", "count_gates",
-    "random_state_c64", "uniforms",
+    "random_state_c64", "uniforms", "probe_phases",
 ]
 
 
@@ -357,3 +357,12 @@ def random_state_c64(n: int, seed: int) -> np.ndarray:
 def uniforms(count: int, seed: int) -> np.ndarray:
     """Seeded uniforms in [0, 1) (float64) for sampling."""
     return np.random.Generator(np.random.PCG64(seed)).random(count)
+
+
+def probe_phases(n: int, seed: int, count: int = 4) -> np.ndarray:
+    """Seeded exponents e in {0, 1, 2, 3}, shape (count, 2^n), uint8: the
+    probe vectors phi_r with entries i^e used to compare two states through a
+    few inner products <phi_r|psi> (a deviation d shows up in them with
+    E|<phi|d>|^2 = |d|^2)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(0, 4, size=(count, 1 << n), dtype=np.uint8)

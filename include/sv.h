@@ -148,7 +148,9 @@ typedef struct {
   uint64_t gates_in;     /* gates given */
   uint64_t passes;       /* fused passes launched */
   uint64_t bytes;        /* algorithmic HBM bytes: 16 * 2^n per pass, 16 * 2^(n-c)
-                            for a controlled pass with c controls */
+                            for a controlled pass with c controls; for sv_batch_run
+                            16 * 2^n per LDS-resident circuit (one read, one write)
+                            plus 16 * 2^n per pass of every other circuit */
   double useful_flops;   /* sum over passes of groups * 2^k (8*2^k - 2), groups =
                             2^(n-k) (2^(n-k-c) for a controlled pass) */
   double fuse_s;         /* host time in the fusion pass */
@@ -160,6 +162,9 @@ typedef struct {
   uint64_t graph_relaunched;  /* 1 when opts.use_graph relaunched the handle's kept
                                  graph without capturing a new one */
   uint64_t variant_bytes[5];  /* with opts.timing: algorithmic bytes per kernel family */
+  uint64_t launches;          /* kernel launches the call issued (inside its graph when it
+                                 ran as one): one per pass for sv_apply_circuit; for
+                                 sv_batch_run one LDS-resident launch plus one per level */
 } sv_run_stats;
 
 /* ---- state -------------------------------------------------------------- */
@@ -309,8 +314,9 @@ int sv_write_amplitudes(sv_state* s, uint64_t start, uint64_t count, const float
  * queued on the stream of states[0], after the work already queued on the
  * other handles' streams; the call returns once it has finished.  All
  * launches are captured in one hipGraph: circuits whose state fits in LDS
- * (n <= the autotuned limit, at most 13 qubits = 64 KiB) run in one
- * workgroup each, entirely on chip, with one HBM read and one write;
+ * (n <= the autotuned limit: at most 14 qubits = 128 KiB, and no more than
+ * the device's LDS per workgroup) run in one workgroup each, entirely on
+ * chip, with one HBM read and one write;
  * larger ones advance one fused pass per launch of a level kernel that
  * covers that pass of every circuit that has one (the kernel boundary is
  * the barrier between a circuit's dependent passes).  On a device failure

@@ -11,7 +11,9 @@ Contents, each written from the paper's definitions:
   Sec. II-A, Eq. 4 (C, complex128, OpenMP over groups, ``sv_oracle.c``);
 * ``norm_sq``: sum |c_i|^2 of Eq. 1 with pairwise FP64 summation;
 * ``compare``: max |delta|, relative L2, infidelity and norm drift of a
-  complex64 state against a complex128 one;
+  complex64 state against a complex128 one; ``probe_projections``: a state's
+  inner products with seeded probe vectors (whole-state checks through a few
+  stored numbers);
 * ``full_unitary`` / ``brute_force_state``: an independent construction of
   the whole 2^n x 2^n circuit operator from Kronecker products (Eq. 3), a
   bit permutation and, for controlled gates, a diagonal projector, for
@@ -164,6 +166,22 @@ def compare(gpu_c64: np.ndarray, ref_c128: np.ndarray) -> dict:
     acc = CompareAcc()
     acc.add(gpu_c64, ref_c128)
     return acc.result()
+
+
+def probe_projections(psi: np.ndarray, phases: np.ndarray) -> np.ndarray:
+    """<phi_r|psi> for probe vectors phi_r with entries i^e (e = phases[r, i]
+    in {0, 1, 2, 3}): sum_i conj(i^e) psi_i, formed as the FP64 sums of psi
+    over each exponent class.  A few such projections check a whole state
+    against a stored reference: a deviation d moves each one by <phi_r|d>,
+    whose mean square is |d|^2."""
+    psi = np.asarray(psi).astype(np.complex128, copy=False)
+    unit = np.array([1, 1j, -1, -1j])
+    out = np.zeros(phases.shape[0], dtype=np.complex128)
+    for r in range(phases.shape[0]):
+        re = np.bincount(phases[r], weights=psi.real, minlength=4)
+        im = np.bincount(phases[r], weights=psi.imag, minlength=4)
+        out[r] = np.sum(np.conj(unit) * (re + 1j * im))
+    return out
 
 
 # ---------------------------------------------------------------------------

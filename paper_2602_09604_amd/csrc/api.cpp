@@ -386,6 +386,7 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
     SV_HIP(hipEventElapsedTime(&ms, s->ev0, s->ev1));
     stats->gpu_s = ms * 1e-3;
     stats->passes = passes.size();
+    stats->launches = passes.size();
     stats->bytes = 0;
     double fl = 0.0;
     for (const Pass& p : passes) {
@@ -700,6 +701,7 @@ int sv_apply_circuit(sv_state* s, const sv_gate* gates, size_t n_gates, const sv
         SV_HIP(hipEventElapsedTime(&ms, s->ev0, s->ev1));
         stats->gpu_s = ms * 1e-3;
         stats->passes = s->graph_passes;
+        stats->launches = s->graph_passes;
         stats->bytes = s->graph_bytes;
         stats->useful_flops = s->graph_flops;
         stats->gates_in = n_gates;

@@ -14,7 +14,7 @@
 //                  the next pass without spinning on device flags).
 // The LDS branch runs on a forked capture stream, so it overlaps the level
 // launches of the large circuits.  The LDS-resident size limit is chosen by
-// the autotuner.
+// the autotuner (up to 14 qubits, 128 KiB, where the device allows it).
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -101,7 +101,7 @@ __device__ void apply_dispatch(PTR2 psi2, PTR4 psi4, const float2* __restrict__ 
   }
 }
 
-// One workgroup per LDS-resident circuit (state of 2^n <= 2^13 amplitudes).
+// One workgroup per LDS-resident circuit (state of 2^n <= 2^14 amplitudes).
 __global__ __launch_bounds__(256) void k_batch_lds(const BCirc* __restrict__ circs, const int* __restrict__ which,
                                                    const BPass* __restrict__ passes, const float2* __restrict__ mats) {
   extern __shared__ float4 st4[];
@@ -141,6 +141,7 @@ __global__ __launch_bounds__(256) void k_batch_level(const BCirc* __restrict__ c
 
 std::mutex g_batch_mu;
 int g_lds_max_n = 12;  // largest LDS-resident state (qubits); set by the autotuner
+constexpr int kBatchLdsMaxQubits = 14;
 
 void fill_pass(BPass& bp, int n, const FusedGate& f, uint32_t mat) {
   int pos[SV_MAX_K];
@@ -175,7 +176,18 @@ int batch_lds_max_n() {
 }
 void set_batch_lds_max_n(int n) {
   std::lock_guard<std::mutex> lk(g_batch_mu);
-  g_lds_max_n = std::max(1, std::min(13, n));
+  g_lds_max_n = std::max(1, std::min(kBatchLdsMaxQubits, n));
+}
+
+// Largest LDS-resident state the current device allows: 8 * 2^n bytes of
+// dynamic LDS per workgroup (gfx950 has 160 KiB per CU), at most 14 qubits.
+int batch_lds_cap() {
+  int dev = 0, bytes = 0;
+  SV_HIP(hipGetDevice(&dev));
+  SV_HIP(hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  int n = 1;
+  while (n < kBatchLdsMaxQubits && ((size_t)8 << (n + 1)) <= (size_t)bytes) ++n;
+  return n;
 }
 
 int plan_fusion(const sv_gate* g, size_t n, int n_qubits, const sv_run_opts& o, std::vector<FusedGate>& fused,
@@ -184,8 +196,8 @@ int plan_fusion(const sv_gate* g, size_t n, int n_qubits, const sv_run_opts& o, 
 // Batched run on explicit buffers; lds_max_n < 0 uses the tuned limit.
 void batch_run_impl(void* const* psis, const int* ns, const sv_gate* const* circuits, const size_t* n_gates,
                     size_t n_circ, const sv_run_opts& o, hipStream_t st, int lds_max_n, double* gpu_s,
-                    uint64_t* passes_out, double* fuse_s) {
-  const int lds_n = lds_max_n < 0 ? batch_lds_max_n() : lds_max_n;
+                    uint64_t* passes_out, double* fuse_s, uint64_t* bytes_out, uint64_t* launches_out) {
+  const int lds_n = std::min(lds_max_n < 0 ? batch_lds_max_n() : lds_max_n, batch_lds_cap());
   const auto t0 = std::chrono::steady_clock::now();
   std::vector<BCirc> circs(n_circ);
   std::vector<BPass> passes;
@@ -322,6 +334,12 @@ void batch_run_impl(void* const* psis, const int* ns, const sv_gate* const* circ
     const BPass* d_pass = (const BPass*)(dev + off_pass);
     const float2* d_mat = (const float2*)(dev + off_mat);
     const bool graph = true;
+    // states above 64 KiB of LDS (14 qubits) need the larger dynamic-LDS
+    // limit set on the kernel before it is captured
+    if (!small.empty() && ((size_t)8 << small_n) > 65536)
+      SV_HIP(hipFuncSetAttribute((const void*)k_batch_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)((size_t)8 << small_n)));
+    uint64_t launches = 0;
     if (graph) SV_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     try {
       hipStream_t sst = st;
@@ -331,6 +349,7 @@ void batch_run_impl(void* const* psis, const int* ns, const sv_gate* const* circ
         sst = side;
       }
       if (!small.empty()) {
+        ++launches;
         hipLaunchKernelGGL(k_batch_lds, dim3((unsigned)small.size()), dim3(256), (size_t)8 << small_n, sst, d_circ,
                            (const int*)(dev + small_off), d_pass, d_mat);
         SV_HIP(hipGetLastError());
@@ -339,6 +358,7 @@ void batch_run_impl(void* const* psis, const int* ns, const sv_gate* const* circ
         const uint64_t blocks = first[L].back();
         if (blocks == 0) continue;
         if (blocks >= ((uint64_t)1 << 31)) throw DeviceError{hipErrorInvalidValue, "batch level too large"};
+        ++launches;
         hipLaunchKernelGGL(k_batch_level, dim3((unsigned)blocks), dim3(256), 0, st, d_circ,
                            (const int*)(dev + lvl_int_off[L]), (const uint64_t*)(dev + lvl_first_off[L]),
                            (int)active[L].size(), L, d_pass, d_mat);
@@ -373,6 +393,13 @@ void batch_run_impl(void* const* psis, const int* ns, const sv_gate* const* circ
       *gpu_s = ms * 1e-3;
     }
     if (passes_out) *passes_out = passes.size();
+    if (launches_out) *launches_out = launches;
+    if (bytes_out) {
+      uint64_t b = 0;
+      for (size_t c = 0; c < n_circ; ++c)
+        b += ((uint64_t)16 << ns[c]) * (ns[c] <= lds_n ? (circs[c].npass > 0 ? 1 : 0) : (uint64_t)circs[c].npass);
+      *bytes_out = b;
+    }
     cleanup();
   } catch (...) {
     cleanup();
@@ -428,8 +455,9 @@ extern "C" int sv_batch_run(sv_state* const* states, const sv_gate* const* circu
       SV_HIP(hipStreamWaitEvent(st0, ev, 0));
     }
     double gpu_s = 0, fuse_s = 0;
-    uint64_t np = 0;
-    batch_run_impl(psis.data(), ns.data(), circuits, n_gates, n_circuits, o, st0, -1, &gpu_s, &np, &fuse_s);
+    uint64_t np = 0, bytes = 0, launches = 0;
+    batch_run_impl(psis.data(), ns.data(), circuits, n_gates, n_circuits, o, st0, -1, &gpu_s, &np, &fuse_s, &bytes,
+                   &launches);
     for (hipEvent_t ev : waits) (void)hipEventDestroy(ev);
     waits.clear();
     for (size_t c = 0; c < n_circuits; ++c) state_note_gates(states[c], circuits[c], n_gates[c]);
@@ -441,6 +469,8 @@ extern "C" int sv_batch_run(sv_state* const* states, const sv_gate* const* circu
       stats->passes = np;
       stats->gpu_s = gpu_s;
       stats->fuse_s = fuse_s;
+      stats->bytes = bytes;
+      stats->launches = launches;
     }
     return SV_OK;
   } catch (const DeviceError& e) {

@@ -29,9 +29,10 @@ bool state_poisoned(sv_state* s);
 void state_poison(sv_state* s);
 int batch_lds_max_n();
 void set_batch_lds_max_n(int n);
+int batch_lds_cap();
 void batch_run_impl(void* const* psis, const int* ns, const sv_gate* const* circuits, const size_t* n_gates,
                     size_t n_circ, const sv_run_opts& o, hipStream_t st, int lds_max_n, double* gpu_s,
-                    uint64_t* passes_out, double* fuse_s);
+                    uint64_t* passes_out, double* fuse_s, uint64_t* bytes_out, uint64_t* launches_out);
 
 namespace {
 
@@ -176,7 +177,7 @@ int sv_autotune(sv_state* s, int budget_ms) {
       const double pi = 3.14159265358979323846;
       std::uniform_real_distribution<double> ang(0.0, 2 * pi);
       int thr = 9;
-      for (int nb = 10; nb <= 13; ++nb) {
+      for (int nb = 10; nb <= std::min(14, batch_lds_cap()); ++nb) {
         const int copies = 64;
         if (((size_t)copies << nb) > ((size_t)1 << n)) break;
         std::vector<std::vector<double>> mats;
@@ -222,10 +223,10 @@ int sv_autotune(sv_state* s, int budget_ms) {
         o.fusion = SV_FUSE_GREEDY;
         double t_lds = 0, t_lvl = 0, best_lds = 1e30, best_lvl = 1e30;
         for (int r = 0; r < 3; ++r) {
-          batch_run_impl(psis.data(), ns.data(), circs.data(), counts.data(), copies, o, st, 13, &t_lds, nullptr,
-                         nullptr);
+          batch_run_impl(psis.data(), ns.data(), circs.data(), counts.data(), copies, o, st, 14, &t_lds, nullptr,
+                         nullptr, nullptr, nullptr);
           batch_run_impl(psis.data(), ns.data(), circs.data(), counts.data(), copies, o, st, 0, &t_lvl, nullptr,
-                         nullptr);
+                         nullptr, nullptr, nullptr);
           best_lds = std::min(best_lds, t_lds);
           best_lvl = std::min(best_lvl, t_lvl);
         }
@@ -313,7 +314,7 @@ int sv_tune_load(const char* path) {
     const size_t bl = text.find("\"batch_lds_max_n\"");
     if (bl != std::string::npos) {
       int v = 0;
-      if (std::sscanf(text.c_str() + text.find(':', bl) + 1, "%d", &v) != 1 || v < 1 || v > 13)
+      if (std::sscanf(text.c_str() + text.find(':', bl) + 1, "%d", &v) != 1 || v < 1 || v > 14)
         return fail(SV_EINVAL, "batch_lds_max_n out of range");
       set_batch_lds_max_n(v);
     }

@@ -51,7 +51,8 @@ class sv_run_stats(ctypes.Structure):
     _fields_ = [("gates_in", ctypes.c_uint64), ("passes", ctypes.c_uint64), ("bytes", ctypes.c_uint64),
                 ("useful_flops", ctypes.c_double), ("fuse_s", ctypes.c_double), ("gpu_s", ctypes.c_double),
                 ("variant_s", ctypes.c_double * 5), ("variant_passes", ctypes.c_uint64 * 5),
-                ("graph_relaunched", ctypes.c_uint64), ("variant_bytes", ctypes.c_uint64 * 5)]
+                ("graph_relaunched", ctypes.c_uint64), ("variant_bytes", ctypes.c_uint64 * 5),
+                ("launches", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}

@@ -20,6 +20,10 @@ def set_lds_limit(tmp_path, n):
     sv.sv_tune_load(str(p))
 
 
+def level_passes(ns, circs, max_k=4, fusion="greedy"):
+    return [len(sv.sv_fuse(c, n, sv.make_opts(max_k=max_k, fusion=fusion))[0]) for n, c in zip(ns, circs)]
+
+
 def run_batch(ns, circs, max_k=4, fusion="greedy"):
     import torch
     stream = torch.cuda.current_stream()
@@ -33,15 +37,21 @@ def run_batch(ns, circs, max_k=4, fusion="greedy"):
     return out, stats
 
 
-@pytest.mark.parametrize("lds_limit", [13, 11, 1])
+@pytest.mark.parametrize("lds_limit", [14, 13, 11, 1])
 def test_batched_ansatz_small(tmp_path, lds_limit):
-    """24 circuits, n in [10, 16]: with limit 13 the small ones stay in LDS and
-    the rest go level by level; with limit 1 everything goes level by level."""
+    """24 circuits, n in [10, 16]: with limit 13 or 14 (128 KiB of LDS per
+    workgroup, where the device allows it) the small ones stay in LDS and the
+    rest go level by level; with limit 1 everything goes level by level."""
     set_lds_limit(tmp_path, lds_limit)
     ns, circs = C.batched_ansatz(24, seed=3, n_min=10, n_max=16)
     out, stats = run_batch(ns, circs)
-    print("limit", lds_limit, "passes", stats["passes"], "gpu_s", stats["gpu_s"], flush=True)
+    print("limit", lds_limit, "passes", stats["passes"], "launches", stats["launches"], "gpu_s", stats["gpu_s"],
+          flush=True)
     assert stats["gates_in"] == sum(len(c) for c in circs)
+    floor = sum(16 << n for n in ns)  # every state read and written once
+    assert stats["bytes"] >= floor
+    if lds_limit == 1:
+        assert stats["bytes"] == sum((16 << n) * p for n, p in zip(ns, level_passes(ns, circs)))
     for n, c, got in zip(ns, circs, out):
         r = oracle.compare(got, oracle.apply_circuit(n, c))
         assert r["max_abs"] <= 1e-5 and r["infidelity"] <= 1e-6, (n, r)
@@ -87,3 +97,40 @@ def test_batch_validation():
         assert sv.sv_batch_run([], [])["passes"] == 0
     finally:
         st.free()
+
+
+GOLD512 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch512_projections.npz")
+
+
+@pytest.mark.parametrize("max_k,fusion", [(4, "block"), (4, "greedy")])
+def test_batch512_every_circuit_against_oracle_projections(max_k, fusion):
+    """All 512 circuits of the batched workload in one sv_batch_run, each
+    checked through 4 inner products with seeded probe vectors against the
+    oracle's full states (tests/golden/make_batch512_projections.py).  A
+    deviation d moves a projection by <phi|d> with mean square |d|^2, so
+    |delta p| <= 1e-4 on 4 probes bounds |d| to about 1e-3 (infidelity
+    about 1e-6) except with negligible probability; norms within 1e-5."""
+    import torch
+    with np.load(GOLD512, allow_pickle=False) as f:
+        gold_ns, proj, norms = f["ns"], f["proj"], f["norm_sq"]
+    ns, circs = C.batched_ansatz(512, seed=0)
+    assert list(gold_ns) == ns
+    stream = torch.cuda.current_stream()
+    states = [sv.State(n, stream=stream) for n in ns]
+    try:
+        stats = sv.sv_batch_run([s.h for s in states], circs, sv.make_opts(max_k=max_k, fusion=fusion))
+        print(fusion, max_k, "passes", stats["passes"], "launches", stats["launches"], "gpu_s", stats["gpu_s"],
+              "bytes / floor", stats["bytes"] / sum(16 << n for n in ns), flush=True)
+        worst = 0.0
+        for c, (n, st) in enumerate(zip(ns, states)):
+            psi = st.read()
+            p = oracle.probe_projections(psi, C.probe_phases(n, 1000 + c, proj.shape[1]))
+            d = float(np.max(np.abs(p - proj[c])))
+            worst = max(worst, d)
+            assert d <= 1e-4, (c, n, d)
+            g2 = float(np.sum(np.abs(psi.astype(np.complex128)) ** 2))
+            assert abs(g2 - norms[c]) <= 1e-5, (c, n, g2)
+        print("worst projection difference", worst, flush=True)
+    finally:
+        for s in states:
+            s.free()

@@ -285,3 +285,39 @@ def test_compare_streaming_equals_one_shot():
     assert abs(one["norm_drift"] - abs(np.vdot(gd, gd).real - 1.0)) < 1e-12
     fid = abs(np.vdot(o, gd)) ** 2 / (np.vdot(o, o).real * np.vdot(gd, gd).real)
     assert abs(one["infidelity"] - (1.0 - fid)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Probe projections (whole-state checks through a few inner products).
+# ---------------------------------------------------------------------------
+def test_probe_projections_definition_and_sensitivity():
+    n = 9
+    ph = C.probe_phases(n, 3, 4)
+    unit = np.array([1, 1j, -1, -1j])
+    # a basis state picks one entry: conj(i^e_x)
+    for x in (0, 77, 511):
+        e = np.zeros(1 << n, dtype=np.complex128)
+        e[x] = 1.0
+        assert np.allclose(oracle.probe_projections(e, ph), np.conj(unit[ph[:, x]]), atol=0, rtol=0)
+    # a random state: the explicit probe vectors' inner products
+    psi = C.random_state_c64(n, 5).astype(np.complex128)
+    phi = unit[ph]
+    assert np.max(np.abs(oracle.probe_projections(psi, ph) - phi.conj() @ psi)) < 1e-14
+    # any deviation of norm 1e-4 moves some projection by more than 1e-5
+    rng = np.random.Generator(np.random.PCG64(9))
+    for _ in range(20):
+        d = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+        d *= 1e-4 / np.linalg.norm(d)
+        assert np.max(np.abs(oracle.probe_projections(psi + d, ph) - oracle.probe_projections(psi, ph))) > 1e-5
+
+
+def test_probe_projections_of_batched_circuit_state():
+    """The oracle path the batch golden file uses, for the batch's circuit
+    family at a size the Kronecker brute force reaches."""
+    rng = np.random.Generator(np.random.PCG64(4))
+    n = 8
+    gates = C.ansatz_circuit(n, rng.uniform(0, 2 * np.pi, size=(3, n, 2)))
+    ph = C.probe_phases(n, 1000, 4)
+    got = oracle.probe_projections(oracle.apply_circuit(n, gates), ph)
+    ref = oracle.probe_projections(oracle.brute_force_state(n, gates), ph)
+    assert np.max(np.abs(got - ref)) < 1e-12

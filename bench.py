@@ -164,6 +164,28 @@ def measured_ceilings(log) -> dict:
     return out
 
 
+def library_sweeps(st, log) -> dict:
+    """The library's own plainest sweeps of the benchmark state: the FP64 norm
+    (read only) and a one-qubit gate on amplitude bit 0 (one contiguous
+    read-modify-write stream, no gather), each the best of three.  They bound
+    what a gate pass on this state can reach on this GPU."""
+    import numpy as np
+    import circuits as C
+    h = np.array([[1, 1], [1, -1]], dtype=np.complex128) / np.sqrt(2.0)
+    nbytes = 16.0 * (1 << st.n)
+    best_pass, best_norm = 1e30, 1e30
+    for _ in range(3):
+        s = st.apply_circuit([C.Gate((0,), h)], fusion="none", precision="fp32_valu", stats=True, timing=True)
+        best_pass = min(best_pass, s["gpu_s"])
+        t0 = time.perf_counter()
+        st.norm()
+        best_norm = min(best_norm, time.perf_counter() - t0)
+    out = {"one_qubit_bit0_pass_GBps": nbytes / best_pass / 1e9,
+           "norm_read_GBps": nbytes / 2 / best_norm / 1e9, "state_qubits": st.n}
+    log("library sweeps:", out)
+    return out
+
+
 def grid30_rows(log) -> dict:
     """The 30-qubit 5x6 depth-20 grid (845 gates): learned fusion in the
     split and FP32 modes and greedy max-k = 6, GPU time and accuracy against
@@ -610,6 +632,8 @@ def main():
         acc["norm_drift"] = extra["norm_drift"]
         extra["accuracy_vs_oracle"] = acc
         log("accuracy vs oracle:", acc)
+    extra["library_sweeps"] = library_sweeps(st, log)
+    extra["dominant_over_best_library_sweep"] = achieved / extra["library_sweeps"]["one_qubit_bit0_pass_GBps"]
     fl = issued_mfma_flops(gates, n, args.max_k, args.fusion, args.precision)
     if fl:
         mfma_s = agg["variant_s"][3] / args.steps

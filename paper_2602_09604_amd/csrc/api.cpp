@@ -28,6 +28,7 @@ struct sv_state {
   double* norm_dev = nullptr;
   double* norm_host = nullptr;  // pinned
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t queued = nullptr;  // recorded after each launched chunk of passes
   // graph of the last use_graph call, with its own device copy of the pass
   // data; a later call whose passes encode to the same bytes relaunches it
   hipGraphExec_t graph_exec = nullptr;
@@ -164,9 +165,8 @@ static std::vector<unsigned char> graph_key(const std::vector<Pass>& passes, con
   f.reserve(passes.size() * 28);
   for (const Pass& p : passes) {
     f.insert(f.end(), {p.k, p.variant, p.precision, (int64_t)p.mat_off, (int64_t)p.mat_bytes, p.tile_bits,
-                       p.reg_iters, p.mfma_cols, p.nhubs, (int64_t)p.cmask, (int64_t)p.cval, p.nmux, p.mfma_x});
+                       p.reg_iters, p.mfma_cols, (int64_t)p.cmask, (int64_t)p.cval, p.nmux, p.mfma_x});
     f.insert(f.end(), p.s, p.s + SV_MAX_K);
-    f.insert(f.end(), p.hub, p.hub + 8);
   }
   std::vector<unsigned char> key(f.size() * sizeof(int64_t) + total);
   std::memcpy(key.data(), f.data(), f.size() * sizeof(int64_t));
@@ -189,12 +189,11 @@ static uint64_t pass_bytes(int n, const Pass& p) { return (uint64_t)16 << (n - c
 static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const sv_run_opts& o,
                        sv_run_stats* stats) {
   // With PHASE fusion every maximal run of pure-phase gates (k <= 2) becomes
-  // one phase pass (or a few, when its cross-chunk terms need more hubs than
-  // one pass holds); everything else is a matrix pass.
+  // one phase pass; everything else is a matrix pass.
   std::vector<Pass> passes;
   std::vector<const double*> mats;               // matrix passes: the fused matrix
   std::vector<std::vector<const double*>> mux;   // multiplexed passes: the matrix of each control value
-  std::vector<std::vector<float>> phase_data;    // phase passes: their tables
+  std::vector<std::vector<unsigned char>> phase_bytes;  // phase passes: their coefficients and table
   size_t total = 0;
   auto add = [&](Pass& p) {
     if (p.variant == V_MFMA) {
@@ -212,20 +211,16 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
       size_t j = i;
       for (; j < fused.size() && phase_gate(fused[j]); ++j)
         poly.add_gate(fused[j].k, fused[j].q, fused[j].mat.data());
-      std::vector<PhaseTables> tabs;
-      phase_tables(poly, s->n, tabs);
-      for (auto& t : tabs) {
-        Pass p;
-        p.k = 0;
-        p.variant = V_PHASE;
-        p.nhubs = t.nhubs;
-        std::copy(t.hub, t.hub + t.nhubs, p.hub);
-        p.mat_bytes = sizeof(float) * t.tab.size();
-        add(p);
-        mats.push_back(nullptr);
-        mux.emplace_back();
-        phase_data.push_back(std::move(t.tab));
-      }
+      Pass p;
+      p.k = 0;
+      p.variant = V_PHASE;
+      p.mat_bytes = phase_data_bytes(s->n);
+      std::vector<unsigned char> bytes(p.mat_bytes);
+      phase_data(poly, s->n, bytes.data());
+      add(p);
+      mats.push_back(nullptr);
+      mux.emplace_back();
+      phase_bytes.push_back(std::move(bytes));
       i = j;
       continue;
     }
@@ -265,7 +260,7 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
         add(p);
         mats.push_back(nullptr);
         mux.push_back(std::move(by_value));
-        phase_data.emplace_back();
+        phase_bytes.emplace_back();
         i = j;
         continue;
       }
@@ -279,7 +274,7 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
       add(p);
       mats.push_back(fused[i].mat.data());
       mux.emplace_back();
-      phase_data.emplace_back();
+      phase_bytes.emplace_back();
       ++i;
       continue;
     }
@@ -292,25 +287,39 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
     add(p);
     mats.push_back(fused[i].mat.data());
     mux.emplace_back();
-    phase_data.emplace_back();
+    phase_bytes.emplace_back();
     ++i;
   }
   if (total == 0) return;
   const size_t base = arena_take(s, total);
-  for (size_t i = 0; i < passes.size(); ++i) {
-    unsigned char* dst = s->arena_host + base + passes[i].mat_off;
+  std::vector<size_t> rel(passes.size());  // offsets of each pass's data from base
+  for (size_t i = 0; i < passes.size(); ++i) rel[i] = passes[i].mat_off;
+  auto encode = [&](size_t i) {
+    unsigned char* dst = s->arena_host + base + rel[i];
     if (passes[i].variant == V_PHASE) {
-      std::memcpy(dst, phase_data[i].data(), passes[i].mat_bytes);
+      std::memcpy(dst, phase_bytes[i].data(), passes[i].mat_bytes);
     } else if (passes[i].nmux > 1) {
       const size_t each = passes[i].mat_bytes / passes[i].nmux;
       for (int v = 0; v < passes[i].nmux; ++v) encode_pass_data(passes[i], mux[i][v], dst + v * each);
     } else {
       encode_pass_data(passes[i], mats[i], dst);
     }
-  }
+  };
   const bool timing = o.timing && stats;
   const bool graph = o.use_graph && !timing;
+  if (timing)
+    while (s->pass_events.size() < 2 * passes.size()) {  // a start and an end per pass
+      hipEvent_t e;
+      SV_HIP(hipEventCreate(&e));
+      s->pass_events.push_back(e);
+    }
+  auto launch = [&](size_t i) {
+    if (timing) SV_HIP(hipEventRecord(s->pass_events[2 * i], s->stream));
+    launch_pass(passes[i], s->n, s->psi, s->arena_dev, s->stream);
+    if (timing) SV_HIP(hipEventRecord(s->pass_events[2 * i + 1], s->stream));
+  };
   if (graph) {
+    for (size_t i = 0; i < passes.size(); ++i) encode(i);
     // The graph reads its pass data from its own buffer, so ring uploads of
     // later calls never disturb it; relaunch when nothing it encodes changed.
     std::vector<unsigned char> key = graph_key(passes, s->arena_host + base, total);
@@ -361,23 +370,28 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
     if (stats) SV_HIP(hipEventRecord(s->ev0, s->stream));
     SV_HIP(hipGraphLaunch(s->graph_exec, s->stream));
   } else {
+    // Passes go out in chunks: the first pass alone, then each time as many
+    // as the host encodes while the GPU still has queued work (an event after
+    // every chunk tells), so encoding hides behind the passes instead of
+    // preceding them.
     for (Pass& p : passes) p.mat_off += base;
-    SV_HIP(hipMemcpyAsync(s->arena_dev + base, s->arena_host + base, total, hipMemcpyHostToDevice, s->stream));
-    if (stats) SV_HIP(hipEventRecord(s->ev0, s->stream));
-  }
-  if (timing) {
-    while (s->pass_events.size() < passes.size() + 1) {
-      hipEvent_t e;
-      SV_HIP(hipEventCreate(&e));
-      s->pass_events.push_back(e);
+    size_t next = 0;
+    while (next < passes.size()) {
+      const size_t lo = next;
+      encode(next++);
+      while (lo > 0 && next < passes.size()) {
+        const hipError_t q = hipEventQuery(s->queued);
+        if (q == hipSuccess) break;  // the GPU ran dry: send what is ready
+        if (q != hipErrorNotReady) throw DeviceError{q, "hipEventQuery"};
+        encode(next++);
+      }
+      const size_t from = rel[lo], to = next < passes.size() ? rel[next] : total;
+      SV_HIP(hipMemcpyAsync(s->arena_dev + base + from, s->arena_host + base + from, to - from,
+                            hipMemcpyHostToDevice, s->stream));
+      if (lo == 0 && stats) SV_HIP(hipEventRecord(s->ev0, s->stream));
+      for (size_t i = lo; i < next; ++i) launch(i);
+      SV_HIP(hipEventRecord(s->queued, s->stream));
     }
-    SV_HIP(hipEventRecord(s->pass_events[0], s->stream));
-    for (size_t i = 0; i < passes.size(); ++i) {
-      launch_pass(passes[i], s->n, s->psi, s->arena_dev, s->stream);
-      SV_HIP(hipEventRecord(s->pass_events[i + 1], s->stream));
-    }
-  } else if (!graph) {
-    for (const Pass& p : passes) launch_pass(p, s->n, s->psi, s->arena_dev, s->stream);
   }
   if (stats) {
     SV_HIP(hipEventRecord(s->ev1, s->stream));
@@ -397,7 +411,7 @@ static void run_passes(sv_state* s, const std::vector<FusedGate>& fused, const s
     if (timing) {
       for (size_t i = 0; i < passes.size(); ++i) {
         float pm = 0.f;
-        SV_HIP(hipEventElapsedTime(&pm, s->pass_events[i], s->pass_events[i + 1]));
+        SV_HIP(hipEventElapsedTime(&pm, s->pass_events[2 * i], s->pass_events[2 * i + 1]));
         const int v = variant_family(passes[i].variant);
         stats->variant_s[v] += pm * 1e-3;
         stats->variant_passes[v] += 1;
@@ -552,6 +566,7 @@ int sv_alloc(int n_qubits, int dtype, void* dev_buf, size_t buf_bytes, void* hip
   SV_HIP(hipHostMalloc(&s->norm_host, sizeof(double), hipHostMallocDefault));
   SV_HIP(hipEventCreate(&s->ev0));
   SV_HIP(hipEventCreate(&s->ev1));
+  SV_HIP(hipEventCreateWithFlags(&s->queued, hipEventDisableTiming));
   // the matrix arena is allocated on the first gate upload
   launch_init_basis(s->psi, s->n, 0, s->stream);
   *out = s;
@@ -585,6 +600,7 @@ int sv_free(sv_state* s) {
   if (s->norm_host) (void)hipHostFree(s->norm_host);
   if (s->ev0) (void)hipEventDestroy(s->ev0);
   if (s->ev1) (void)hipEventDestroy(s->ev1);
+  if (s->queued) (void)hipEventDestroy(s->queued);
   for (hipEvent_t e : s->pass_events) (void)hipEventDestroy(e);
   if (s->meas_dev) (void)hipFree(s->meas_dev);
   if (s->meas_host) (void)hipHostFree(s->meas_host);

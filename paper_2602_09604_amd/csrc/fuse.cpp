@@ -386,12 +386,87 @@ void greedy_partition(const sv_gate* g, size_t n, int max_k, std::vector<std::ve
 // blocked) and from every other gate of the front (horizontal fusion).  A
 // remaining controlled gate is a pass of its own as soon as it reaches the
 // front.
+// Absorbed-gate counts of one search step, keyed by the qubit set (never
+// 0): open addressing with linear probing, emptied by advancing a stamp, so
+// the thousands of lookups per step neither allocate nor rehash often.
+class CountMemo {
+ public:
+  template <class Eval>
+  int get(uint64_t S, Eval&& eval) {
+    if (2 * (used_ + 1) > key_.size()) grow();
+    size_t i = slot(S);
+    while (stamp_[i] == gen_) {
+      if (key_[i] == S) return val_[i];
+      i = (i + 1) & (key_.size() - 1);
+    }
+    const int c = eval(S);
+    stamp_[i] = gen_;
+    key_[i] = S;
+    val_[i] = c;
+    ++used_;
+    return c;
+  }
+  void clear() {
+    used_ = 0;
+    if (++gen_ == 0) {  // the stamp wrapped: forget every slot explicitly
+      std::fill(stamp_.begin(), stamp_.end(), 0u);
+      gen_ = 1;
+    }
+  }
+  size_t size() const { return used_; }
+  template <class F>
+  void for_each(F&& f) const {
+    for (size_t i = 0; i < key_.size(); ++i)
+      if (stamp_[i] == gen_) f(key_[i], val_[i]);
+  }
+
+ private:
+  size_t slot(uint64_t x) const {
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    return (size_t)x & (key_.size() - 1);
+  }
+  void grow() {
+    std::vector<uint64_t> k;
+    std::vector<int> v;
+    for_each([&](uint64_t a, int b) {
+      k.push_back(a);
+      v.push_back(b);
+    });
+    const size_t cap = std::max<size_t>(1024, 2 * key_.size());
+    key_.assign(cap, 0);
+    val_.assign(cap, 0);
+    stamp_.assign(cap, 0u);
+    gen_ = 1;
+    used_ = 0;
+    for (size_t j = 0; j < k.size(); ++j) {
+      size_t i = slot(k[j]);
+      while (stamp_[i] == gen_) i = (i + 1) & (cap - 1);
+      stamp_[i] = gen_;
+      key_[i] = k[j];
+      val_[i] = v[j];
+      ++used_;
+    }
+  }
+  std::vector<uint64_t> key_;
+  std::vector<int> val_;
+  std::vector<uint32_t> stamp_;
+  size_t used_ = 0;
+  uint32_t gen_ = 1;
+};
+
 namespace {
 struct BlockSearch {
   const sv_gate* g;
   std::vector<uint64_t> masks;
   std::vector<char> diag;  // diagonal gates (candidates for control absorption)
   std::vector<int> live;   // indices of gates not yet emitted, in order
+  // the qubit masks and kinds of the live gates, in live order: the scans
+  // below read these two arrays front to back instead of the gate structs
+  std::vector<uint64_t> live_mask;
+  std::vector<unsigned char> live_kind;
+  static constexpr unsigned char kControlled = 1, kDiagonal = 2;
 
   // Gates absorbed by S (indices into g, in order); optionally the candidate
   // qubit additions seen before S is fully blocked.
@@ -400,24 +475,41 @@ struct BlockSearch {
   // max_ctrl qubits outside S (at or above kCtrlMinBit): those become control
   // bits of the pass, which then applies one matrix per control value.
   int max_ctrl = 0;
+  CountMemo memo;  // scratch for the beam steps run on this search
+
+  // refresh live_mask / live_kind after live changed
+  void sync_live() {
+    live_mask.resize(live.size());
+    live_kind.resize(live.size());
+    for (size_t i = 0; i < live.size(); ++i) {
+      const int h = live[i];
+      live_mask[i] = masks[h];
+      live_kind[i] = (g[h].cmask ? kControlled : 0) | (diag[h] ? kDiagonal : 0);
+    }
+  }
 
   int absorb(uint64_t S, std::vector<int>* got, std::vector<uint64_t>* adds) const {
     uint64_t blocked = 0, ctrl = 0;
     int count = 0;
-    for (int h : live) {
-      const uint64_t qh = masks[h];
+    const size_t L = live.size();
+    const uint64_t* lm = live_mask.data();
+    const unsigned char* lk = live_kind.data();
+    for (size_t i = 0; i < L; ++i) {
       if ((S & ~blocked) == 0) break;  // every qubit of S is blocked: nothing more can join
-      if ((qh & blocked) == 0 && !g[h].cmask) {
+      const uint64_t qh = lm[i];
+      const unsigned kind = lk[i];
+      if ((qh & blocked) == 0 && !(kind & kControlled)) {
         const uint64_t out = qh & ~S;
-        if (out == 0 || (max_ctrl > 0 && diag[h] && (qh & S) && (out & kCtrlLowBits) == 0 &&
+        if (out == 0 || (max_ctrl > 0 && (kind & kDiagonal) && (qh & S) && (out & kCtrlLowBits) == 0 &&
                          __builtin_popcountll(ctrl | out) <= max_ctrl)) {
           ctrl |= out;
           ++count;
-          if (got) got->push_back(h);
+          if (got) got->push_back(live[i]);
           continue;
         }
       }
-      if (adds && !g[h].cmask && (qh & S & (narrow ? ~blocked : ~(uint64_t)0)) && (qh & ~S)) adds->push_back(qh & ~S);
+      if (adds && !(kind & kControlled) && (qh & S & (narrow ? ~blocked : ~(uint64_t)0)) && (qh & ~S))
+        adds->push_back(qh & ~S);
       blocked |= qh;
     }
     return count;
@@ -430,9 +522,9 @@ namespace {
 std::vector<int> front_of(const BlockSearch& b) {
   std::vector<int> front;
   uint64_t blocked = 0;
-  for (int h : b.live) {
-    if ((b.masks[h] & blocked) == 0) front.push_back(h);
-    blocked |= b.masks[h];
+  for (size_t i = 0; i < b.live.size(); ++i) {
+    if ((b.live_mask[i] & blocked) == 0) front.push_back(b.live[i]);
+    blocked |= b.live_mask[i];
   }
   return front;
 }
@@ -489,6 +581,7 @@ void init_search(BlockSearch& b, const sv_gate* g, size_t n, int max_ctrl) {
     if (max_ctrl > 0) b.diag[i] = is_diagonal_gate(g[i]);
     b.live.push_back((int)i);
   }
+  b.sync_live();
 }
 }  // namespace
 
@@ -500,6 +593,7 @@ void maxblock_partition(const sv_gate* g, size_t n, int max_k, bool narrow, std:
   b.narrow = narrow;
   std::vector<char> done(n, 0);
   std::vector<uint64_t> adds;
+  CountMemo memo;
   while (!b.live.empty()) {
     const std::vector<int> front = front_of(b);
     std::vector<int> chosen;
@@ -511,13 +605,9 @@ void maxblock_partition(const sv_gate* g, size_t n, int max_k, bool narrow, std:
     if (chosen.empty()) {
       int best_count = -1;
       uint64_t best_S = 0;
-      std::unordered_map<uint64_t, int> memo;  // absorbed-gate counts of this pass
+      memo.clear();  // absorbed-gate counts of this pass
       auto count_of = [&](uint64_t S) {
-        auto it = memo.find(S);
-        if (it != memo.end()) return it->second;
-        const int c = b.absorb(S, nullptr, nullptr);
-        memo.emplace(S, c);
-        return c;
+        return memo.get(S, [&](uint64_t T) { return b.absorb(T, nullptr, nullptr); });
       };
       for (int f : front) {
         if (g[f].cmask) continue;
@@ -535,6 +625,7 @@ void maxblock_partition(const sv_gate* g, size_t n, int max_k, bool narrow, std:
     for (int h : b.live)
       if (!done[h]) rest.push_back(h);
     b.live.swap(rest);
+    b.sync_live();
     blocks.push_back(std::move(chosen));
   }
 }
@@ -560,6 +651,7 @@ struct BeamNode {
 void beam_expand(BlockSearch& b, const BeamNode& nd, int max_k, int topm, std::vector<uint64_t>& adds,
                  std::vector<char>& taken, std::vector<BeamNode>& kids) {
   b.live = nd.live;
+  b.sync_live();
   const std::vector<int> front = front_of(b);
   std::vector<uint64_t> moves;  // candidate sets; 0 stands for a controlled front gate
   int ctrl = -1;
@@ -569,25 +661,24 @@ void beam_expand(BlockSearch& b, const BeamNode& nd, int max_k, int topm, std::v
       break;
     }
   if (ctrl < 0) {
-    std::unordered_map<uint64_t, int> memo;
+    CountMemo& memo = b.memo;
+    memo.clear();
     auto count_of = [&](uint64_t S) {
-      auto it = memo.find(S);
-      if (it != memo.end()) return it->second;
-      const int c = b.absorb(S, nullptr, nullptr);
-      memo.emplace(S, c);
-      return c;
+      return memo.get(S, [&](uint64_t T) { return b.absorb(T, nullptr, nullptr); });
     };
     for (int f : front) (void)grow_from(b, front, f, max_k, count_of, adds);
     std::vector<std::pair<int, uint64_t>> ranked;
     ranked.reserve(memo.size());
-    for (const auto& kv : memo) ranked.push_back({kv.second, kv.first});
-    std::sort(ranked.begin(), ranked.end(), [](const std::pair<int, uint64_t>& x, const std::pair<int, uint64_t>& y) {
+    memo.for_each([&](uint64_t S, int c) { ranked.push_back({c, S}); });
+    // the topm best in the total order below (count, then size, then mask)
+    const size_t top = std::min(ranked.size(), (size_t)topm);
+    std::partial_sort(ranked.begin(), ranked.begin() + top, ranked.end(), [](const std::pair<int, uint64_t>& x, const std::pair<int, uint64_t>& y) {
       if (x.first != y.first) return x.first > y.first;
       const int bx = __builtin_popcountll(x.second), by = __builtin_popcountll(y.second);
       if (bx != by) return bx < by;
       return x.second < y.second;
     });
-    for (size_t i = 0; i < ranked.size() && (int)moves.size() < topm; ++i)
+    for (size_t i = 0; i < top; ++i)
       if (ranked[i].first > 0) moves.push_back(ranked[i].second);
   } else {
     moves.push_back(0);

@@ -233,7 +233,7 @@ void launch_pass(const Pass& p, int n, void* psi, const unsigned char* arena_dev
   } else if (p.variant == V_SHFL) {
     launch_shfl(p, n, psi, reinterpret_cast<const float2*>(data), st);
   } else if (p.variant == V_PHASE) {
-    launch_phase(n, psi, data, p.nhubs, p.hub, st);
+    launch_phase(n, psi, data, st);
   } else if (p.variant == V_LDS) {
     launch_lds(p, n, psi, reinterpret_cast<const float2*>(data), st);
   } else if (const int tm = reg_exchange_mask(n, p.k, p.s)) {

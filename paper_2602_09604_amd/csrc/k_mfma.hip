@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <type_traits>
 
 #include "k_common.h"
@@ -57,6 +58,39 @@ float host_bf16_to_f(uint16_t h) {
   float f;
   std::memcpy(&f, &u, 4);
   return f;
+}
+// IEEE binary16 from binary32, round to nearest even, by integer arithmetic
+// (the compiler's own conversion is a library call on the host, ten times
+// slower than the rest of the encoding).
+uint16_t host_f16(float f) {
+  uint32_t x;
+  std::memcpy(&x, &f, 4);
+  const uint32_t sign = (x >> 16) & 0x8000u;
+  x &= 0x7FFFFFFFu;
+  if (x >= 0x47800000u) return (uint16_t)(sign | (x > 0x7F800000u ? 0x7E00u : 0x7C00u));  // >= 2^16, inf, NaN
+  if (x < 0x38800000u) {  // below 2^-14: a subnormal half (or zero); the float add rounds to even
+    float t;
+    std::memcpy(&t, &x, 4);
+    t += 0.5f;  // 0.5 has the exponent that leaves the subnormal half's bits at the bottom
+    uint32_t u;
+    std::memcpy(&u, &t, 4);
+    return (uint16_t)(sign | (u - 0x3F000000u));
+  }
+  x += 0xC8000FFFu + ((x >> 13) & 1u);  // rebias the exponent by 15 - 127, round to nearest even
+  return (uint16_t)(sign | (x >> 13));
+}
+float host_f16_to_f(uint16_t h) {
+  const uint32_t e = (h >> 10) & 0x1Fu, m = h & 0x3FFu;
+  float f;
+  if (e == 0) {
+    f = std::ldexp((float)m, -24);
+  } else if (e == 31) {
+    f = m ? std::numeric_limits<float>::quiet_NaN() : std::numeric_limits<float>::infinity();
+  } else {
+    const uint32_t u = ((e + 112u) << 23) | (m << 13);
+    std::memcpy(&f, &u, 4);
+  }
+  return (h & 0x8000u) ? -f : f;
 }
 
 // ---- device-side conversions (gfx950 converts to bf16 natively, RNE) -------
@@ -703,10 +737,8 @@ void mfma_encode(const Pass& p, const double* mat, unsigned char* dst) {
             hi = host_bf16((float)v);
             lo = host_bf16((float)(v - (double)host_bf16_to_f(hi)));
           } else {
-            const _Float16 fh = (_Float16)v;
-            const _Float16 fl = (_Float16)((v - (double)(float)fh) * (double)kF16LoScale);
-            std::memcpy(&hi, &fh, 2);
-            std::memcpy(&lo, &fl, 2);
+            hi = host_f16((float)v);
+            lo = host_f16((float)((v - (double)host_f16_to_f(hi)) * (double)kF16LoScale));
           }
           const size_t base = (((size_t)(mt * ks_n + s) * 2) * 64 + lane) * 8 + e;
           o[base] = hi;

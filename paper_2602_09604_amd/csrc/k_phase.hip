@@ -1,7 +1,20 @@
 // Phase-only pass: psi[i] *= exp(2 pi i theta(i)) with theta (in turns) a
-// quadratic polynomial of the bits of i, evaluated from LDS chunk tables
-// (see phase.cpp).  An elementwise, perfectly coalesced sweep: no groups, no
-// matrix, one read and one write per amplitude.
+// quadratic polynomial of the bits of i: c + sum_q alpha_q x_q +
+// sum_{a<b} beta_ab x_a x_b (phase.cpp builds it from a run of diagonal
+// gates).  An elementwise, perfectly coalesced sweep: one read and one write
+// per amplitude, any number of interacting pairs in one pass.
+//
+// The grid covers a low span of 2^lb amplitudes (lb = min(n, 24)) and walks
+// it 2^(n - lb) times, once per value k of the high bits, so a thread's low
+// index bits never change.  Split x = xL + (k << lb):
+//   theta(x) = theta(xL) + theta_high(k) + sum_j k_j gamma_j(xL),
+//   gamma_j(xL) = sum_{a in L} beta_{a, lb+j} x_a.
+// A thread owns the amplitudes base + {0, 1, 512, 513} (bits 0 and 9 free in
+// base), so it evaluates theta(base), the two bit-0 / bit-9 increments and
+// gamma_j(base) once, in FP64, from the coefficients in LDS; bits 10.. of
+// base are the block's, and their sums are formed once per block.  Each sweep
+// then costs a few adds per amplitude plus the sine and cosine: the bit-0 and
+// bit-9 parts of sum_j k_j gamma_j come from the per-k table.
 #include "k_common.h"
 
 namespace sv {
@@ -11,10 +24,10 @@ using kern::gld;
 using kern::gst;
 
 struct PhaseArgs {
-  uint64_t pairs;                // float4 elements
-  int nch;                       // 8-bit chunks that carry index bits
-  int nhubs;
-  int hub[kPhaseHubs];
+  uint64_t pairs;  // float4 elements of the state
+  int n;
+  int lb;          // low span: 2^lb amplitudes per sweep of the grid
+  int nh;          // high bits n - lb
 };
 
 __device__ __forceinline__ float2 rotate(const float2 v, float turns) {
@@ -23,82 +36,110 @@ __device__ __forceinline__ float2 rotate(const float2 v, float turns) {
   return make_float2(v.x * c - v.y * s, v.x * s + v.y * c);
 }
 
-// The two amplitudes i0 = 2e and i1 = 2e + 1 of float4 element e.  Chunks
-// 1.. of their index are equal, so the chunk-1.. table sums are shared; only
-// the chunk-0 entries (and a hub on bit 0) differ.  Within a wavefront the
-// 128 indices share chunks 1.., so those LDS reads are broadcasts.  Every
-// table entry is a fraction of a turn in [0, 1); partial sums are folded
-// back into [0, 1) so the FP32 sum keeps ~2^-23 turn resolution.
-__device__ __forceinline__ float4 phase_pair(const float* __restrict__ T, const float* __restrict__ R,
-                                             const PhaseArgs& a, uint64_t e, const float4 v) {
-  const uint64_t i0 = 2 * e;
-  const int lo0 = (int)(i0 & 255);
-  int idx[kPhaseChunks];
-#pragma unroll
-  for (int c = 1; c < kPhaseChunks; ++c) idx[c] = (int)((i0 >> (8 * c)) & 255);
-  float u = 0.f;
-#pragma unroll
-  for (int c = 1; c < kPhaseChunks; ++c)
-    if (c < a.nch) u += T[c * 256 + idx[c]];
-  u -= floorf(u);
-  float t0 = u + T[lo0], t1 = u + T[lo0 + 1];
-  for (int h = 0; h < a.nhubs; ++h) {
-    const float* Rh = R + h * kPhaseChunks * 256;
-    float sh = 0.f;
-#pragma unroll
-    for (int c = 1; c < kPhaseChunks; ++c)
-      if (c < a.nch) sh += Rh[c * 256 + idx[c]];
-    const int hb = a.hub[h];
-    const float x0 = (float)((i0 >> hb) & 1), x1 = (float)(((i0 | 1) >> hb) & 1);
-    t0 = fmaf(x0, sh + Rh[lo0], t0);
-    t1 = fmaf(x1, sh + Rh[lo0 + 1], t1);
-    t0 -= floorf(t0);
-    t1 -= floorf(t1);
-  }
-  const float2 lo = rotate(make_float2(v.x, v.y), t0);
-  const float2 hi = rotate(make_float2(v.z, v.w), t1);
-  return make_float4(lo.x, lo.y, hi.x, hi.y);
-}
+__device__ __forceinline__ float fold(double t) { return (float)(t - rint(t)); }
 
-// Two elements per thread per iteration, both loads issued before any math.
 template <bool NT>
-__global__ __launch_bounds__(256) void k_phase(float4* __restrict__ psi, const float4* __restrict__ tab,
+__global__ __launch_bounds__(256) void k_phase(float4* __restrict__ psi, const unsigned char* __restrict__ data,
                                                const PhaseArgs a) {
-  extern __shared__ float4 tl4[];
-  const float* tl = reinterpret_cast<const float*>(tl4);
-  const int floats = kPhaseChunks * 256 * (1 + a.nhubs);
-  for (int i = threadIdx.x; i < floats / 4; i += 256) tl4[i] = tab[i];
+  __shared__ double s_beta[kPhaseMaxQ * kPhaseMaxQ];
+  __shared__ double s_alpha[kPhaseMaxQ];
+  __shared__ double s_rho[kPhaseMaxQ];  // sum over the block's set bits b >= 10 of beta[q][b]
+  __shared__ double s_theta_p;          // c + the polynomial on the block's bits alone
+  const double* coef = reinterpret_cast<const double*>(data);
+  const int n = a.n;
+  for (int i = threadIdx.x; i < kPhaseMaxQ * kPhaseMaxQ; i += 256) s_beta[i] = coef[1 + kPhaseMaxQ + i];
+  if (threadIdx.x < kPhaseMaxQ) s_alpha[threadIdx.x] = coef[1 + threadIdx.x];
   __syncthreads();
-  const float* T = tl;
-  const float* R = tl + kPhaseChunks * 256;
-  const uint64_t stride = (uint64_t)gridDim.x * 512;
-  for (uint64_t e0 = (uint64_t)blockIdx.x * 512 + threadIdx.x; e0 < a.pairs; e0 += stride) {
-    const uint64_t e1 = e0 + 256;
-    const bool has1 = e1 < a.pairs;
-    const float4 v0 = gld<NT>(psi + e0);
-    const float4 v1 = has1 ? gld<NT>(psi + e1) : make_float4(0.f, 0.f, 0.f, 0.f);
-    gst<NT>(psi + e0, phase_pair(T, R, a, e0, v0));
-    if (has1) gst<NT>(psi + e1, phase_pair(T, R, a, e1, v1));
+  const uint64_t pbits = (uint64_t)blockIdx.x << 10;  // amplitude bits 10 .. lb-1 of this block
+  if (threadIdx.x < kPhaseMaxQ) {
+    const int q = threadIdx.x;
+    double r = 0.0;
+    for (int b = 10; b < a.lb; ++b)
+      if ((pbits >> b) & 1) r += s_beta[q * kPhaseMaxQ + b];
+    s_rho[q] = r;
+  } else if (threadIdx.x == 64) {
+    double t = coef[0];
+    for (int b = 10; b < a.lb; ++b) {
+      if (!((pbits >> b) & 1)) continue;
+      t += s_alpha[b];
+      for (int b2 = 10; b2 < b; ++b2)
+        if ((pbits >> b2) & 1) t += s_beta[b * kPhaseMaxQ + b2];
+    }
+    s_theta_p = t;
+  }
+  __syncthreads();
+
+  // this thread's low part: bits 1..8 from the thread, 10.. from the block
+  const uint64_t e0 = (uint64_t)blockIdx.x * 512 + threadIdx.x;
+  const uint64_t base = 2 * e0;
+  const int lq = a.lb < 9 ? a.lb : 9;  // thread bits 1 .. lq-1
+  double th = s_theta_p, g0 = s_alpha[0] + s_rho[0], g9 = s_alpha[9] + s_rho[9];
+  for (int q = 1; q < lq; ++q) {
+    if (!((base >> q) & 1)) continue;
+    double r = s_alpha[q] + s_rho[q];
+    for (int q2 = 1; q2 < q; ++q2)
+      if ((base >> q2) & 1) r += s_beta[q * kPhaseMaxQ + q2];
+    th += r;
+    g0 += s_beta[q];
+    g9 += s_beta[9 * kPhaseMaxQ + q];
+  }
+  // bit 9 exists only from 10 qubits up; its coefficients are zero below
+  const double b09 = s_beta[9];
+  const float t00 = fold(th), t10 = fold(th + g0), t01 = fold(th + g9), t11 = fold(th + g0 + g9 + b09);
+  float gam[kPhaseMaxHigh];
+#pragma unroll
+  for (int j = 0; j < kPhaseMaxHigh; ++j) {
+    gam[j] = 0.f;
+    if (j < a.nh) {
+      const int b = a.lb + j;
+      double r = s_rho[b];
+      for (int q = 1; q < lq; ++q)
+        if ((base >> q) & 1) r += s_beta[b * kPhaseMaxQ + q];
+      gam[j] = fold(r);
+    }
+  }
+
+  const float4* tab = reinterpret_cast<const float4*>(data + kPhaseCoefBytes);
+  const uint64_t span = (uint64_t)1 << (a.lb - 1);  // elements per sweep of the grid
+  const uint64_t sweeps = (uint64_t)1 << a.nh;
+  for (uint64_t k = 0; k < sweeps; ++k) {
+    const uint64_t f0 = e0 + k * span, f1 = f0 + 256;
+    const bool ok0 = f0 < a.pairs, ok1 = f1 < a.pairs;  // false only below 10 qubits
+    const float4 v0 = ok0 ? gld<NT>(psi + f0) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 v1 = ok1 ? gld<NT>(psi + f1) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 hk = tab[k];
+    float G = hk.x;
+#pragma unroll
+    for (int j = 0; j < kPhaseMaxHigh; ++j) {
+      if (j < a.nh && ((k >> j) & 1)) G += gam[j];
+      if ((j & 3) == 3) G -= rintf(G);  // keep the sum small: full FP32 resolution
+    }
+    if (ok0) {
+      const float2 lo = rotate(make_float2(v0.x, v0.y), t00 + G);
+      const float2 hi = rotate(make_float2(v0.z, v0.w), t10 + G + hk.y);
+      gst<NT>(psi + f0, make_float4(lo.x, lo.y, hi.x, hi.y));
+    }
+    if (ok1) {
+      const float2 lo = rotate(make_float2(v1.x, v1.y), t01 + G + hk.z);
+      const float2 hi = rotate(make_float2(v1.z, v1.w), t11 + G + hk.y + hk.z);
+      gst<NT>(psi + f1, make_float4(lo.x, lo.y, hi.x, hi.y));
+    }
   }
 }
 
 }  // namespace
 
-void launch_phase(int n, void* psi, const unsigned char* data, int nhubs, const int* hubs, hipStream_t st) {
+void launch_phase(int n, void* psi, const unsigned char* data, hipStream_t st) {
   PhaseArgs a{};
   a.pairs = (uint64_t)1 << (n - 1);
-  a.nch = (n + 7) / 8;
-  a.nhubs = nhubs;
-  for (int h = 0; h < nhubs; ++h) a.hub[h] = hubs[h];
-  uint64_t blocks = (a.pairs + 511) / 512;
-  if (blocks > 4096) blocks = 4096;
-  const size_t lds = sizeof(float) * kPhaseChunks * 256 * (1 + nhubs);
+  a.n = n;
+  a.lb = phase_low_bits(n);
+  a.nh = n - a.lb;
+  const unsigned blocks = a.lb > 10 ? 1u << (a.lb - 10) : 1u;  // 512 elements (1024 amplitudes) per block
   if (n >= kern::kNtMinQubits)
-    hipLaunchKernelGGL(k_phase<true>, dim3((unsigned)blocks), dim3(256), lds, st, (float4*)psi,
-                       (const float4*)data, a);
+    hipLaunchKernelGGL(k_phase<true>, dim3(blocks), dim3(256), 0, st, (float4*)psi, data, a);
   else
-    hipLaunchKernelGGL(k_phase<false>, dim3((unsigned)blocks), dim3(256), lds, st, (float4*)psi,
-                       (const float4*)data, a);
+    hipLaunchKernelGGL(k_phase<false>, dim3(blocks), dim3(256), 0, st, (float4*)psi, data, a);
   SV_HIP(hipGetLastError());
 }
 

@@ -8,13 +8,13 @@
 // (fuse_phase) and the device applies a whole run as one elementwise pass
 // (k_phase).
 //
-// Device tables: the index is cut into 8-bit chunks.  theta(i) =
-//   sum_c T_c[chunk_c(i)]                      (linear + same-chunk terms)
-// + sum_h x_h(i) * sum_c R_hc[chunk_c(i)]      (cross-chunk terms by hub h)
-// where the hubs are a vertex cover of the cross-chunk interaction graph.
+// The device receives the coefficients themselves (every pair, no limit on
+// how many pairs interact) plus a small table over the index bits above the
+// span one grid sweep covers; k_phase evaluates the rest per thread.
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstring>
 
 #include "sv_internal.h"
 
@@ -65,69 +65,41 @@ void PhasePoly::add_gate(int k, const int* q, const double* mat) {
   }
 }
 
-void phase_tables(const PhasePoly& p, int n, std::vector<PhaseTables>& out) {
-  out.clear();
-  auto chunk = [](int q) { return q >> 3; };
-  // cross-chunk pairs and a greedy vertex cover (highest remaining degree first)
-  std::vector<std::pair<int, int>> cross;
-  for (int a = 0; a < n; ++a)
-    for (int b = a + 1; b < n; ++b)
-      if (wrap(p.beta[a][b]) != 0.0 && chunk(a) != chunk(b)) cross.push_back({a, b});
-  std::vector<int> owner(cross.size(), -1), hubs;
-  while (true) {
-    std::vector<int> deg(n, 0);
-    for (size_t e = 0; e < cross.size(); ++e)
-      if (owner[e] < 0) {
-        ++deg[cross[e].first];
-        ++deg[cross[e].second];
-      }
-    const int h = (int)(std::max_element(deg.begin(), deg.end()) - deg.begin());
-    if (deg[h] == 0) break;
-    for (size_t e = 0; e < cross.size(); ++e)
-      if (owner[e] < 0 && (cross[e].first == h || cross[e].second == h)) owner[e] = h;
-    hubs.push_back(h);
+void phase_data(const PhasePoly& p, int n, unsigned char* out) {
+  // angles in turns, folded into [-1/2, 1/2) (sums of a few stay small, so
+  // FP32 keeps ~2^-24 turn resolution on the device)
+  auto turns = [](double a) {
+    double t = wrap(a) / kTwoPi;
+    return t >= 0.5 ? t - 1.0 : t;
+  };
+  std::memset(out, 0, kPhaseCoefBytes);
+  double* coef = reinterpret_cast<double*>(out);
+  double* alpha = coef + 1;
+  double* beta = alpha + kPhaseMaxQ;
+  const int m = std::min(n, (int)p.alpha.size());
+  coef[0] = turns(p.c);
+  for (int a = 0; a < m; ++a) {
+    alpha[a] = turns(p.alpha[a]);
+    for (int b = a + 1; b < m; ++b) beta[(size_t)a * kPhaseMaxQ + b] = beta[(size_t)b * kPhaseMaxQ + a] = turns(p.beta[a][b]);
   }
-  const size_t npass = std::max<size_t>(1, (hubs.size() + kPhaseHubs - 1) / kPhaseHubs);
-  const double turn = 1.0 / kTwoPi;
-  for (size_t pi = 0; pi < npass; ++pi) {
-    PhaseTables t;
-    t.tab.assign(kPhaseTableFloats, 0.f);
-    std::vector<double> T((size_t)kPhaseChunks * 256, 0.0);
-    std::vector<double> R((size_t)kPhaseHubs * kPhaseChunks * 256, 0.0);
-    if (pi == 0) {
-      // linear and same-chunk quadratic terms, plus the global phase in chunk 0
-      for (int c = 0; c < kPhaseChunks; ++c)
-        for (int v = 0; v < 256; ++v) {
-          double th = c == 0 ? p.c : 0.0;
-          for (int bit = 0; bit < 8; ++bit) {
-            const int a = 8 * c + bit;
-            if (a >= n || !((v >> bit) & 1)) continue;
-            th += p.alpha[a];
-            for (int bit2 = bit + 1; bit2 < 8; ++bit2) {
-              const int b = 8 * c + bit2;
-              if (b < n && ((v >> bit2) & 1)) th += p.beta[a][b];
-            }
-          }
-          T[(size_t)c * 256 + v] = th;
-        }
+  const int lb = phase_low_bits(n), nh = n - lb;
+  float* tab = reinterpret_cast<float*>(out + kPhaseCoefBytes);
+  auto B = [&](int a, int b) { return beta[(size_t)a * kPhaseMaxQ + b]; };
+  for (uint64_t k = 0; k < ((uint64_t)1 << nh); ++k) {
+    double th = 0.0, b0 = 0.0, b9 = 0.0;
+    for (int j = 0; j < nh; ++j) {
+      if (!((k >> j) & 1)) continue;
+      const int q = lb + j;
+      th += alpha[q];
+      for (int j2 = 0; j2 < j; ++j2)
+        if ((k >> j2) & 1) th += B(lb + j2, q);
+      b0 += B(0, q);
+      if (n > 9) b9 += B(9, q);
     }
-    for (size_t hi = pi * kPhaseHubs; hi < std::min(hubs.size(), (pi + 1) * kPhaseHubs); ++hi) {
-      const int h = hubs[hi];
-      const int slot = (int)(hi - pi * kPhaseHubs);
-      t.hub[slot] = h;
-      t.nhubs = slot + 1;
-      for (size_t e = 0; e < cross.size(); ++e) {
-        if (owner[e] != h) continue;
-        const int other = cross[e].first == h ? cross[e].second : cross[e].first;
-        const double bb = p.beta[std::min(h, other)][std::max(h, other)];
-        const int c = chunk(other), bit = other & 7;
-        for (int v = 0; v < 256; ++v)
-          if ((v >> bit) & 1) R[((size_t)slot * kPhaseChunks + c) * 256 + v] += bb;
-      }
-    }
-    for (size_t i = 0; i < T.size(); ++i) t.tab[i] = (float)(wrap(T[i]) * turn);
-    for (size_t i = 0; i < R.size(); ++i) t.tab[T.size() + i] = (float)(wrap(R[i]) * turn);
-    out.push_back(std::move(t));
+    tab[4 * k + 0] = (float)(th - std::nearbyint(th));
+    tab[4 * k + 1] = (float)(b0 - std::nearbyint(b0));
+    tab[4 * k + 2] = (float)(b9 - std::nearbyint(b9));
+    tab[4 * k + 3] = 0.f;
   }
 }
 

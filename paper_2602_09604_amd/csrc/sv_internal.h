@@ -63,9 +63,6 @@ struct Pass {
   int tile_bits = 13;                    // LDS: log2 amplitudes per tile
   int reg_iters = 1;                     // REG: groups per thread
   int mfma_cols = 32;                    // MFMA: groups per wavefront tile
-  // phase passes
-  int nhubs = 0;
-  int hub[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   // controlled passes: act only where (index & cmask) == cval
   uint64_t cmask = 0;
   uint64_t cval = 0;
@@ -187,19 +184,21 @@ struct PhasePoly {
   explicit PhasePoly(int n = 0) : alpha(n, 0.0), beta(n, std::vector<double>(n, 0.0)) {}
   void add_gate(int k, const int* q, const double* mat);
 };
-// Device tables of one phase pass (angles in turns); returns the passes needed
-// (a polynomial whose cross-chunk terms need more than kPhaseHubs hub qubits is
-// split).
-constexpr int kPhaseChunks = 5;  // 8-bit chunks of the index: n <= 40
-constexpr int kPhaseHubs = 8;
-constexpr size_t kPhaseTableFloats = (size_t)kPhaseChunks * 256 + (size_t)kPhaseHubs * kPhaseChunks * 256;
-struct PhaseTables {
-  int nhubs = 0;
-  int hub[kPhaseHubs] = {0};
-  std::vector<float> tab;  // kPhaseTableFloats: T[chunk][256], then R[hub][chunk][256]
-};
-void phase_tables(const PhasePoly& p, int n, std::vector<PhaseTables>& out);
-void launch_phase(int n, void* psi, const unsigned char* data, int nhubs, const int* hubs, hipStream_t st);
+// Device data of one phase pass (angles in turns, each folded into
+// [-1/2, 1/2)): the polynomial's coefficients as doubles -- c, alpha[q] and
+// beta[a][b] stored symmetrically, kPhaseMaxQ wide -- then, for the index
+// bits above the low span of 2^lb amplitudes one grid sweep covers
+// (lb = phase_low_bits(n)), one float4 per value k of those bits:
+// (theta_high(k), sum_j k_j beta[0][lb + j], sum_j k_j beta[9][lb + j], 0),
+// where theta_high is the polynomial on the high bits alone without c.
+constexpr int kPhaseMaxQ = SV_MAX_QUBITS;
+constexpr int kPhaseLowBits = 24;
+constexpr int kPhaseMaxHigh = kPhaseMaxQ - kPhaseLowBits;
+constexpr size_t kPhaseCoefBytes = ((1 + kPhaseMaxQ + (size_t)kPhaseMaxQ * kPhaseMaxQ) * sizeof(double) + 15) / 16 * 16;
+inline int phase_low_bits(int n) { return n < kPhaseLowBits ? n : kPhaseLowBits; }
+inline size_t phase_data_bytes(int n) { return kPhaseCoefBytes + 16 * ((size_t)1 << (n - phase_low_bits(n))); }
+void phase_data(const PhasePoly& p, int n, unsigned char* out);
+void launch_phase(int n, void* psi, const unsigned char* data, hipStream_t st);
 void launch_ctrl(const Pass& p, int n, void* psi, const float2* U, hipStream_t st);
 bool shfl_eligible(int n, int k, const int* s);
 void launch_shfl(const Pass& p, int n, void* psi, const float2* U, hipStream_t st);

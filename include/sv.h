@@ -78,8 +78,9 @@ extern "C" {
  * lets a block take diagonal gates that reach up to 3 qubits outside its
  * targets (at bit 4 or above) as control bits: such a block is one gate per
  * control value on the same targets, and sv_apply_circuit runs all of them
- * as one matrix-core launch when the block has k >= 4 targets.  PHASE is GREEDY in which pure-phase diagonal gates of at
- * most two qubits (CZ, CP, RZ, Z, S, T, ...) never block one another: those
+ * as one matrix-core launch when the block has k >= 4 targets.  PHASE is
+ * GREEDY in which pure-phase diagonal gates of at most two qubits (CZ, CP,
+ * RZ, Z, S, T, ...) never block one another: those
  * that fit join dense blocks, the others are gathered into phase blocks of
  * any width.  sv_fuse returns a phase block as its canonical diagonal gates
  * (one CP-form gate per interacting pair, one diagonal per qubit); in

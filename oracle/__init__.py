@@ -18,6 +18,9 @@ Contents, each written from the paper's definitions:
   the whole 2^n x 2^n circuit operator from Kronecker products (Eq. 3), a
   bit permutation and, for controlled gates, a diagonal projector, for
   n <= 10;
+* ``diagonal_factors``: what a run of diagonal gates multiplies chosen
+  amplitudes by (Eq. 4 with a diagonal matrix: the entry the index selects),
+  for sampled checks of phase passes at any size;
 * ``pauli_expectation``, ``marginal_probabilities``, ``sample_indices``:
   the plain definitions of what the state-reading kernels return;
 * ``ghz_amplitudes``, ``qft_like_amplitudes``, ``grover_amplitudes``: closed
@@ -239,6 +242,28 @@ _PX = np.array([[0, 1], [1, 0]], dtype=np.complex128)
 _PY = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
 _PZ = np.array([[1, 0], [0, -1]], dtype=np.complex128)
 
+
+
+def diagonal_factors(gates, idx) -> np.ndarray:
+    """For diagonal gates applied in order, the factor each amplitude index
+    in ``idx`` is multiplied by: by Eq. 4 a diagonal U maps c_i to
+    U[l, l] c_i, l the index's bits at the gate's qubits (qubits[j] -> bit j),
+    and only where the controls match; the product over the gates."""
+    idx = np.asarray(idx, dtype=np.uint64)
+    out = np.ones(idx.shape, dtype=np.complex128)
+    for g in gates:
+        u = np.asarray(g.matrix, dtype=np.complex128)
+        assert np.count_nonzero(u - np.diag(np.diag(u))) == 0, "diagonal gates only"
+        l = np.zeros(idx.shape, dtype=np.int64)
+        for j, q in enumerate(g.qubits):
+            l |= ((idx >> np.uint64(q)) & np.uint64(1)).astype(np.int64) << j
+        f = np.diag(u)[l]
+        cmask, cval = int(getattr(g, "cmask", 0) or 0), int(getattr(g, "cval", 0) or 0)
+        if cmask:
+            on = (idx & np.uint64(cmask)) == np.uint64(cval)
+            f = np.where(on, f, 1.0)
+        out *= f
+    return out
 
 def pauli_expectation(psi: np.ndarray, n: int, xmask: int, zmask: int) -> complex:
     """<psi|P|psi> for the Pauli string with X on the qubits of xmask only, Z

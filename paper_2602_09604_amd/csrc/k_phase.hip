@@ -4,9 +4,12 @@
 // gates).  An elementwise, perfectly coalesced sweep: one read and one write
 // per amplitude, any number of interacting pairs in one pass.
 //
-// The grid covers a low span of 2^lb amplitudes (lb = min(n, 24)) and walks
+// The grid covers a low span of 2^lb amplitudes (lb = min(n, 28)) and walks
 // it 2^(n - lb) times, once per value k of the high bits, so a thread's low
-// index bits never change.  Split x = xL + (k << lb):
+// index bits never change.  (Measured at 34 qubits: spans of 2^21, 2^22,
+// 2^24, 2^26, 2^28, 2^30 amplitudes ran at 0.64, 0.67, 0.72, 0.74, 0.76,
+// 0.77 of HBM peak; the whole state as one span, 0.28 at 32 qubits, pays
+// the per-thread setup for every four amplitudes.)  Split x = xL + (k << lb):
 //   theta(x) = theta(xL) + theta_high(k) + sum_j k_j gamma_j(xL),
 //   gamma_j(xL) = sum_{a in L} beta_{a, lb+j} x_a.
 // A thread owns the amplitudes base + {0, 1, 512, 513} (bits 0 and 9 free in
@@ -102,12 +105,22 @@ __global__ __launch_bounds__(256) void k_phase(float4* __restrict__ psi, const u
   const float4* tab = reinterpret_cast<const float4*>(data + kPhaseCoefBytes);
   const uint64_t span = (uint64_t)1 << (a.lb - 1);  // elements per sweep of the grid
   const uint64_t sweeps = (uint64_t)1 << a.nh;
+  const bool ok0 = e0 < a.pairs, ok1 = e0 + 256 < a.pairs;  // false only below 10 qubits
+  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+  // the next sweep's two elements and table entry are loaded before this
+  // sweep's math, so a wave keeps four 16-byte loads in flight and never
+  // waits on the table
+  float4 v0 = ok0 ? gld<NT>(psi + e0) : zero;
+  float4 v1 = ok1 ? gld<NT>(psi + e0 + 256) : zero;
+  float4 hk = tab[0];
   for (uint64_t k = 0; k < sweeps; ++k) {
     const uint64_t f0 = e0 + k * span, f1 = f0 + 256;
-    const bool ok0 = f0 < a.pairs, ok1 = f1 < a.pairs;  // false only below 10 qubits
-    const float4 v0 = ok0 ? gld<NT>(psi + f0) : make_float4(0.f, 0.f, 0.f, 0.f);
-    const float4 v1 = ok1 ? gld<NT>(psi + f1) : make_float4(0.f, 0.f, 0.f, 0.f);
-    const float4 hk = tab[k];
+    float4 n0 = zero, n1 = zero, nk = zero;
+    if (k + 1 < sweeps) {  // ok0 and ok1 hold whenever there is a next sweep
+      n0 = gld<NT>(psi + f0 + span);
+      n1 = gld<NT>(psi + f1 + span);
+      nk = tab[k + 1];
+    }
     float G = hk.x;
 #pragma unroll
     for (int j = 0; j < kPhaseMaxHigh; ++j) {
@@ -124,6 +137,9 @@ __global__ __launch_bounds__(256) void k_phase(float4* __restrict__ psi, const u
       const float2 hi = rotate(make_float2(v1.z, v1.w), t11 + G + hk.y + hk.z);
       gst<NT>(psi + f1, make_float4(lo.x, lo.y, hi.x, hi.y));
     }
+    v0 = n0;
+    v1 = n1;
+    hk = nk;
   }
 }
 

@@ -192,7 +192,7 @@ struct PhasePoly {
 // (theta_high(k), sum_j k_j beta[0][lb + j], sum_j k_j beta[9][lb + j], 0),
 // where theta_high is the polynomial on the high bits alone without c.
 constexpr int kPhaseMaxQ = SV_MAX_QUBITS;
-constexpr int kPhaseLowBits = 24;
+constexpr int kPhaseLowBits = 28;
 constexpr int kPhaseMaxHigh = kPhaseMaxQ - kPhaseLowBits;
 constexpr size_t kPhaseCoefBytes = ((1 + kPhaseMaxQ + (size_t)kPhaseMaxQ * kPhaseMaxQ) * sizeof(double) + 15) / 16 * 16;
 inline int phase_low_bits(int n) { return n < kPhaseLowBits ? n : kPhaseLowBits; }

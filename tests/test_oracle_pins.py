@@ -321,3 +321,27 @@ def test_probe_projections_of_batched_circuit_state():
     got = oracle.probe_projections(oracle.apply_circuit(n, gates), ph)
     ref = oracle.probe_projections(oracle.brute_force_state(n, gates), ph)
     assert np.max(np.abs(got - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_diagonal_factors_against_brute_force(seed):
+    """diagonal_factors against the Kronecker-product construction: from the
+    uniform superposition every amplitude is 2^(-n/2) times the factor.  The
+    mix holds a diagonal gate that is not symmetric in its qubits (so a
+    swapped qubit order fails) and a controlled diagonal gate."""
+    n = 7
+    rng = np.random.Generator(np.random.PCG64(40 + seed))
+    gates = []
+    for _ in range(12):
+        a, b = (int(v) for v in rng.choice(n, 2, replace=False))
+        gates.append(C.Gate((a, b), C.CP(float(rng.uniform(0, 2 * np.pi)))))
+    gates.append(C.Gate((1, 5), np.diag(np.exp(1j * np.array([0.1, 0.7, 1.9, 2.6])))))
+    gates.append(C.Gate((3,), C.RZ(0.4), (0, 6), (1, 0)))
+    gates += [C.Gate((q,), C.RZ(float(rng.uniform(0, 2 * np.pi)))) for q in range(n)]
+    idx = np.arange(1 << n)
+    psi = oracle.brute_force_state(n, [C.Gate((q,), C.H) for q in range(n)] + gates)
+    f = oracle.diagonal_factors(gates, idx)
+    assert np.max(np.abs(psi - f * 2.0 ** (-n / 2))) < 1e-13
+    swapped = [C.Gate(tuple(reversed(g.qubits)), g.matrix, g.controls, g.control_values) if g.k == 2 else g
+               for g in gates]
+    assert np.max(np.abs(oracle.diagonal_factors(swapped, idx) - f)) > 1e-3

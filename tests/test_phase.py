@@ -116,10 +116,9 @@ def test_phase_heavy_random_circuits(seed):
 @pytest.mark.gpu
 @pytest.mark.parametrize("n", [26, 28])
 def test_phase_pass_all_pairs_one_sweep(n):
-    """Controlled phases between random qubit pairs (every distance, across
-    the low span of 2^24 amplitudes one grid sweep covers and the high bits
-    walked sweep by sweep) plus one-qubit phases and a general diagonal
-    two-qubit gate: the whole run is one phase pass, against the oracle."""
+    """Controlled phases between random qubit pairs (every distance) plus
+    one-qubit phases and a general diagonal two-qubit gate: the whole run is
+    one phase pass, against the oracle's full state."""
     rng = np.random.Generator(np.random.PCG64(n))
     gates = [C.Gate((q,), C.H) for q in range(n)]
     phases = []
@@ -142,6 +141,53 @@ def test_phase_pass_all_pairs_one_sweep(n):
         assert r["max_abs"] <= 1e-5 and r["infidelity"] <= 1e-6, r
     finally:
         st.free()
+
+
+def phase_run(n, rng, pairs):
+    gates = []
+    for _ in range(pairs):
+        a, b = (int(v) for v in rng.choice(n, 2, replace=False))
+        gates.append(C.Gate((a, b), C.CP(float(rng.uniform(0, 2 * np.pi)))))
+    gates += [C.Gate((q,), C.RZ(float(rng.uniform(0, 2 * np.pi)))) for q in range(n)]
+    gates.append(C.Gate((0, n - 1), np.diag(np.exp(1j * rng.uniform(0, 2 * np.pi, 4)))))
+    gates.append(C.Gate((9, n - 2), np.diag(np.exp(1j * rng.uniform(0, 2 * np.pi, 4)))))
+    gates.append(C.Gate((n - 3, 1), C.CZ))
+    return gates
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n", [30, 32])
+def test_phase_pass_high_bits_sampled(n):
+    """Above the low span one grid sweep covers (2^28 amplitudes) the pass
+    walks the high index bits sweep by sweep.  From the uniform superposition
+    every amplitude is 2^(-n/2) times the product of the diagonal entries its
+    index selects (oracle.diagonal_factors): checked on 4096 random indices
+    and the first and last 2^16 amplitudes, relative to 2^(-n/2)."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(300 + n))
+    phases = phase_run(n, rng, 200)
+    gates = [C.Gate((q,), C.H) for q in range(n)] + phases
+    st = sv.State(n)
+    try:
+        s = st.apply_circuit(gates, max_k=6, fusion="phase", precision="fp32_valu", timing=True)
+        assert s["variant_passes"][4] == 1
+        scale = 2.0 ** (n / 2)
+        worst, ms = 0.0, []
+        idx = np.unique(rng.integers(0, 1 << n, 4096, dtype=np.uint64))
+        got = np.array([st.read(int(i), 1)[0] for i in idx])
+        blocks = [(idx, got)]
+        for start in (0, (1 << n) - (1 << 16)):
+            blocks.append((np.arange(start, start + (1 << 16), dtype=np.uint64), st.read(start, 1 << 16)))
+        for ix, g in blocks:
+            rel = np.abs(g.astype(np.complex128) * scale - oracle.diagonal_factors(phases, ix))
+            worst = max(worst, float(rel.max()))
+            ms.append(float(np.mean(rel ** 2)))
+        print(n, "phase pass", s["variant_s"][4], "max rel", worst, "mean sq", max(ms), flush=True)
+        assert worst <= 1e-5 and max(ms) <= 1e-10, (worst, ms)
+    finally:
+        st.free()
+        del st
+        torch.cuda.empty_cache()
 
 
 @pytest.mark.gpu

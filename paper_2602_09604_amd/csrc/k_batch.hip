@@ -119,8 +119,12 @@ __global__ __launch_bounds__(256) void k_batch_lds(const BCirc* __restrict__ cir
   for (int i = threadIdx.x; i < pairs; i += 256) g4[i] = st4[i];
 }
 
-// Pass `level` of every circuit in `active` (count entries); first_block is
-// the prefix sum of workgroups per active circuit (count + 1 entries).
+// Pass `level` of every circuit in `active` (count entries), all of one
+// shape <K, MODE>; first_block is the prefix sum of workgroups per active
+// circuit (count + 1 entries).  One instantiation per shape keeps each
+// launch free of the shape dispatch (a call with a stack frame, and the
+// register budget of the largest shape).
+template <int K, int MODE>
 __global__ __launch_bounds__(256) void k_batch_level(const BCirc* __restrict__ circs, const int* __restrict__ active,
                                                      const uint64_t* __restrict__ first_block, int count, int level,
                                                      const BPass* __restrict__ passes,
@@ -136,7 +140,30 @@ __global__ __launch_bounds__(256) void k_batch_level(const BCirc* __restrict__ c
   const BPass p = passes[c.pass0 + level];
   const uint64_t g = (b - first_block[lo]) * 256 + threadIdx.x;
   if (g >= p.items) return;
-  apply_dispatch(c.psi, reinterpret_cast<float4*>(c.psi), mats + p.mat, p, g);
+  apply_item<K, MODE>(c.psi, reinterpret_cast<float4*>(c.psi), mats + p.mat, p, g);
+}
+
+// the pass shapes the batch supports: index mode * 8 + K
+constexpr int kShapes = 24;
+bool shape_supported(int mode, int K) {
+  return (mode == 0 && K >= 1 && K <= 5) || (mode == 1 && K >= 0 && K <= 5) || (mode == 2 && K == 6);
+}
+
+void launch_level(int shape, unsigned blocks, hipStream_t st, const BCirc* circs, const int* active,
+                  const uint64_t* first, int count, int level, const BPass* passes, const float2* mats) {
+#define SV_LEVEL(K_, M_)                                                                                     \
+  case M_ * 8 + K_:                                                                                          \
+    hipLaunchKernelGGL((k_batch_level<K_, M_>), dim3(blocks), dim3(256), 0, st, circs, active, first, count, \
+                       level, passes, mats);                                                                  \
+    break;
+  switch (shape) {
+    SV_LEVEL(1, 0) SV_LEVEL(2, 0) SV_LEVEL(3, 0) SV_LEVEL(4, 0) SV_LEVEL(5, 0)
+    SV_LEVEL(0, 1) SV_LEVEL(1, 1) SV_LEVEL(2, 1) SV_LEVEL(3, 1) SV_LEVEL(4, 1) SV_LEVEL(5, 1)
+    SV_LEVEL(6, 2)
+    default: throw DeviceError{hipErrorInvalidValue, "batch: unsupported pass shape"};
+  }
+#undef SV_LEVEL
+  SV_HIP(hipGetLastError());
 }
 
 std::mutex g_batch_mu;
@@ -257,20 +284,36 @@ void batch_run_impl(void* const* psis, const int* ns, const sv_gate* const* circ
     if (ns[c] <= lds_n && circs[c].npass > 0) small.push_back((int)c);
   int small_n = 1;
   for (int c : small) small_n = std::max(small_n, ns[c]);
-  std::vector<std::vector<int>> active(max_levels);
-  std::vector<std::vector<uint64_t>> first(max_levels);
+  // per level, one launch per pass shape present: the active large circuits
+  // whose pass at that level has the shape, with their workgroup prefix sums
+  struct Launch {
+    int level, shape;
+    std::vector<int> active;
+    std::vector<uint64_t> first;
+  };
+  std::vector<Launch> launch_list;
   size_t level_ints = 0, level_u64 = 0;
   for (int L = 0; L < max_levels; ++L) {
-    uint64_t acc = 0;
+    std::vector<int> slot(kShapes, -1);
     for (size_t c = 0; c < n_circ; ++c) {
       if (ns[c] <= lds_n || circs[c].npass <= L) continue;
-      active[L].push_back((int)c);
-      first[L].push_back(acc);
-      acc += (passes[circs[c].pass0 + L].items + 255) / 256;
+      const BPass& bp = passes[circs[c].pass0 + L];
+      if (!shape_supported(bp.mode, bp.K)) throw std::invalid_argument("sv_batch_run: unsupported pass shape");
+      const int sh = bp.mode * 8 + bp.K;
+      if (slot[sh] < 0) {
+        slot[sh] = (int)launch_list.size();
+        launch_list.push_back(Launch{L, sh, {}, {}});
+      }
+      Launch& l = launch_list[slot[sh]];
+      const uint64_t acc = l.first.empty() ? 0 : l.first.back();
+      if (l.first.empty()) l.first.push_back(0);
+      l.active.push_back((int)c);
+      l.first.push_back(acc + (bp.items + 255) / 256);
     }
-    first[L].push_back(acc);
-    level_ints += active[L].size();
-    level_u64 += first[L].size();
+  }
+  for (auto& l : launch_list) {
+    level_ints += l.active.size();
+    level_u64 += l.first.size();
   }
   // one device buffer: circuits | passes | first-block prefixes | ints | matrices
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
@@ -283,15 +326,16 @@ void batch_run_impl(void* const* psis, const int* ns, const sv_gate* const* circ
   std::vector<unsigned char> host(total, 0);
   std::memcpy(host.data() + off_circ, circs.data(), sizeof(BCirc) * n_circ);
   std::memcpy(host.data() + off_pass, passes.data(), sizeof(BPass) * passes.size());
-  std::vector<size_t> lvl_first_off(max_levels), lvl_int_off(max_levels);
+  std::vector<size_t> lvl_first_off(launch_list.size()), lvl_int_off(launch_list.size());
   size_t fu = 0, iu = 0;
-  for (int L = 0; L < max_levels; ++L) {
-    lvl_first_off[L] = off_first + sizeof(uint64_t) * fu;
-    std::memcpy(host.data() + lvl_first_off[L], first[L].data(), sizeof(uint64_t) * first[L].size());
-    fu += first[L].size();
-    lvl_int_off[L] = off_int + sizeof(int) * iu;
-    std::memcpy(host.data() + lvl_int_off[L], active[L].data(), sizeof(int) * active[L].size());
-    iu += active[L].size();
+  for (size_t i = 0; i < launch_list.size(); ++i) {
+    const Launch& l = launch_list[i];
+    lvl_first_off[i] = off_first + sizeof(uint64_t) * fu;
+    std::memcpy(host.data() + lvl_first_off[i], l.first.data(), sizeof(uint64_t) * l.first.size());
+    fu += l.first.size();
+    lvl_int_off[i] = off_int + sizeof(int) * iu;
+    std::memcpy(host.data() + lvl_int_off[i], l.active.data(), sizeof(int) * l.active.size());
+    iu += l.active.size();
   }
   const size_t small_off = off_int + sizeof(int) * iu;
   std::memcpy(host.data() + small_off, small.data(), sizeof(int) * small.size());
@@ -354,15 +398,14 @@ void batch_run_impl(void* const* psis, const int* ns, const sv_gate* const* circ
                            (const int*)(dev + small_off), d_pass, d_mat);
         SV_HIP(hipGetLastError());
       }
-      for (int L = 0; L < max_levels; ++L) {
-        const uint64_t blocks = first[L].back();
+      for (size_t i = 0; i < launch_list.size(); ++i) {
+        const Launch& l = launch_list[i];
+        const uint64_t blocks = l.first.back();
         if (blocks == 0) continue;
         if (blocks >= ((uint64_t)1 << 31)) throw DeviceError{hipErrorInvalidValue, "batch level too large"};
         ++launches;
-        hipLaunchKernelGGL(k_batch_level, dim3((unsigned)blocks), dim3(256), 0, st, d_circ,
-                           (const int*)(dev + lvl_int_off[L]), (const uint64_t*)(dev + lvl_first_off[L]),
-                           (int)active[L].size(), L, d_pass, d_mat);
-        SV_HIP(hipGetLastError());
+        launch_level(l.shape, (unsigned)blocks, st, d_circ, (const int*)(dev + lvl_int_off[i]),
+                     (const uint64_t*)(dev + lvl_first_off[i]), (int)l.active.size(), l.level, d_pass, d_mat);
       }
       if (graph && !small.empty()) {  // join
         SV_HIP(hipEventRecord(join, side));

@@ -339,8 +339,9 @@ def batch_figures(max_k: int) -> dict:
 
 def profile_workload(name: str, tune_qubits: int) -> None:
     """One 32-qubit workload of other_workloads() (or the 30-qubit grid at a
-    small greedy max k, whose passes are all k <= 3), after the autotuner, run
-    twice (the second run is the one to read in a kernel trace).  It starts
+    small greedy max k, whose passes are all k <= 3, or the 512-circuit
+    batch), after the autotuner, run twice (the second run is the one to
+    read in a kernel trace).  It starts
     with a copy of known size (8 GiB read, 8 GiB written) that calibrates
     the HBM byte counters of rocprofv3 --pmc runs."""
     import torch
@@ -357,6 +358,9 @@ def profile_workload(name: str, tune_qubits: int) -> None:
     scratch.free()
     del scratch
     torch.cuda.empty_cache()
+    if name == "batch512":  # the batched workload (its own warm-up run first)
+        log("batch512:", batch_figures(4))
+        return
     n = 32
     init = 0
     if name.startswith("grid30"):
@@ -509,8 +513,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-workload", default=None,
                     choices=["qft32_greedy", "qft32_phase", "grover32", "qv32_greedy", "qv32_learned",
-                             "grid30_greedy2", "grid30_greedy3"],
-                    help="autotune, then run one 30/32-qubit workload twice and exit (for rocprofv3 runs)")
+                             "grid30_greedy2", "grid30_greedy3", "batch512"],
+                    help="autotune, then run one 30/32-qubit workload twice (or the 512-circuit batch) and exit "
+                         "(for rocprofv3 runs)")
     ap.add_argument("--profile-step", action="store_true",
                     help="counter-calibration copy + one untimed step, then exit (for rocprofv3 --pmc runs)")
     args = ap.parse_args()

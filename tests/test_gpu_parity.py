@@ -287,6 +287,32 @@ def test_fp16x3_range_guard():
         st.free()
 
 
+def test_empty_circuit_and_identity_gates():
+    """No gates: every fusion mode, with and without a graph or timing, leaves
+    the state bit for bit as written and reports no passes.  Identity gates
+    (dense, controlled, diagonal) keep it to rounding."""
+    sv = _sv()
+    n = 12
+    st = sv.State(n)
+    try:
+        psi = C.random_state_c64(n, 4)
+        st.write(0, psi)
+        for kw in (dict(fusion="none"), dict(fusion="greedy", max_k=6), dict(fusion="learned", max_k=6),
+                   dict(fusion="phase"), dict(fusion="block", use_graph=True), dict(fusion="greedy", timing=True)):
+            s = st.apply_circuit([], stats=True, **kw)
+            assert s["passes"] == 0 and s["gates_in"] == 0 and s["bytes"] == 0, (kw, s)
+            assert np.array_equal(st.read(), psi), kw
+        eye = [C.Gate((3,), np.eye(2)), C.Gate((0, 7), np.eye(4)), C.Gate((2, 9, 11), np.eye(8)),
+               C.Gate((5,), np.eye(2), (1, 6), (1, 0)), C.Gate((4, 8), C.CP(0.0))]
+        for kw in (dict(fusion="none"), dict(fusion="greedy", max_k=4, precision="fp16x3"),
+                   dict(fusion="phase", max_k=2)):
+            st.write(0, psi)
+            st.apply_circuit(eye, **kw)
+            check(st.read(), psi.astype(np.complex128))
+    finally:
+        st.free()
+
+
 def test_validation_leaves_state_untouched():
     sv = _sv()
     st = sv.State(10)

@@ -11,7 +11,9 @@
 //                  grid is filled by the whole batch instead of by one state.
 //                  The kernel boundary is the barrier between dependent passes
 //                  of a circuit (it also makes every XCD's writes visible to
-//                  the next pass without spinning on device flags).
+//                  the next pass without spinning on device flags).  A level
+//                  is one launch per pass shape; k_batch_level_x is the
+//                  lane-exchange form for targets on amplitude bits 1..3.
 // The LDS branch runs on a forked capture stream, so it overlaps the level
 // launches of the large circuits.  The LDS-resident size limit is chosen by
 // the autotuner (up to 14 qubits, 128 KiB, where the device allows it).
@@ -46,6 +48,7 @@ struct BPass {
   uint64_t stride[SV_MAX_K];
   uint32_t mat;               // float2 index of the complex64 matrix
   int mode, K;
+  int tm;                     // element bits 0..2 among the targets (lane exchange), 0: none
 };
 
 struct BCirc {
@@ -143,14 +146,105 @@ __global__ __launch_bounds__(256) void k_batch_level(const BCirc* __restrict__ c
   apply_item<K, MODE>(c.psi, reinterpret_cast<float4*>(c.psi), mats + p.mat, p, g);
 }
 
+// The same with targets on element bits 0..2 (set TM): the lane exchange of
+// k_common.h, so that every load and store instruction covers whole lines.
+// A wave's 64 work items belong to one circuit (items are a multiple of 64).
+template <int K, int MODE, int TM>
+__global__ __launch_bounds__(256) void k_batch_level_x(const BCirc* __restrict__ circs, const int* __restrict__ active,
+                                                       const uint64_t* __restrict__ first_block, int count, int level,
+                                                       const BPass* __restrict__ passes,
+                                                       const float2* __restrict__ mats) {
+  constexpr int D = 1 << K;
+  constexpr int M = LowBits<TM>::m;
+  constexpr int XM = (1 << M) - 1;
+  static_assert(M <= K, "every low target is an element-space target");
+  const uint64_t b = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first_block[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const BCirc c = circs[active[lo]];
+  const BPass p = passes[c.pass0 + level];
+  const uint64_t wave0 = (b - first_block[lo]) * 256 + (threadIdx.x & ~63u);
+  if (wave0 >= p.items) return;
+  float4* __restrict__ psi = reinterpret_cast<float4*>(c.psi);
+  const float2* __restrict__ U = mats + p.mat;
+  const int j = threadIdx.x & 63;
+  const int uj = compress_bits<6>(j, ~TM & 63), cj = compress_bits<6>(j, TM);
+  uint64_t offc = 0;
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+    if ((cj >> i) & 1) offc += p.stride[i];
+  uint64_t xoff[XM + 1];
+#pragma unroll
+  for (int X = 0; X <= XM; ++X) xoff[X] = insert_zeros<K, uint64_t>((uint64_t)X << (6 - M), p.lowmask);
+  const uint64_t b0 = insert_zeros<K, uint64_t>(wave0 + uj, p.lowmask) + offc;
+  float4 v[D];
+#pragma unroll
+  for (int r = 0; r < D; ++r) v[r] = psi[b0 + xoff[r & XM] + local_offset<K, uint64_t>(r & ~XM, p.stride)];
+  xtranspose<TM>(v, j);
+#pragma unroll
+  for (int h0 = 0; h0 < D; h0 += XM + 1) {
+    float4 o[XM + 1];
+#pragma unroll
+    for (int x = 0; x <= XM; ++x) o[x] = pair_row<K, MODE>(v, U, h0 | x);
+    xtranspose<TM>(o, j);
+#pragma unroll
+    for (int x = 0; x <= XM; ++x) psi[b0 + xoff[x] + local_offset<K, uint64_t>(h0, p.stride)] = o[x];
+  }
+}
+
 // the pass shapes the batch supports: index mode * 8 + K
-constexpr int kShapes = 24;
+constexpr int kShapes = 8 * 24;
 bool shape_supported(int mode, int K) {
   return (mode == 0 && K >= 1 && K <= 5) || (mode == 1 && K >= 0 && K <= 5) || (mode == 2 && K == 6);
 }
 
+template <int K, int MODE, int TM>
+void launch_x(unsigned blocks, hipStream_t st, const BCirc* circs, const int* active, const uint64_t* first,
+              int count, int level, const BPass* passes, const float2* mats) {
+  if constexpr (LowBits<TM>::m <= K)
+    hipLaunchKernelGGL((k_batch_level_x<K, MODE, TM>), dim3(blocks), dim3(256), 0, st, circs, active, first, count,
+                       level, passes, mats);
+  else
+    throw DeviceError{hipErrorInvalidValue, "batch: low targets"};
+}
+
+template <int K, int MODE>
+void launch_xk(int tm, unsigned blocks, hipStream_t st, const BCirc* circs, const int* active, const uint64_t* first,
+               int count, int level, const BPass* passes, const float2* mats) {
+  switch (tm) {
+    case 1: return launch_x<K, MODE, 1>(blocks, st, circs, active, first, count, level, passes, mats);
+    case 2: return launch_x<K, MODE, 2>(blocks, st, circs, active, first, count, level, passes, mats);
+    case 3: return launch_x<K, MODE, 3>(blocks, st, circs, active, first, count, level, passes, mats);
+    case 4: return launch_x<K, MODE, 4>(blocks, st, circs, active, first, count, level, passes, mats);
+    case 5: return launch_x<K, MODE, 5>(blocks, st, circs, active, first, count, level, passes, mats);
+    case 6: return launch_x<K, MODE, 6>(blocks, st, circs, active, first, count, level, passes, mats);
+    case 7: return launch_x<K, MODE, 7>(blocks, st, circs, active, first, count, level, passes, mats);
+    default: throw DeviceError{hipErrorInvalidValue, "batch: low targets"};
+  }
+}
+
 void launch_level(int shape, unsigned blocks, hipStream_t st, const BCirc* circs, const int* active,
                   const uint64_t* first, int count, int level, const BPass* passes, const float2* mats) {
+  const int tm = shape / 24, sh = shape % 24;
+  if (tm) {
+    switch (sh) {
+      case 0 * 8 + 1: launch_xk<1, 0>(tm, blocks, st, circs, active, first, count, level, passes, mats); break;
+      case 0 * 8 + 2: launch_xk<2, 0>(tm, blocks, st, circs, active, first, count, level, passes, mats); break;
+      case 0 * 8 + 3: launch_xk<3, 0>(tm, blocks, st, circs, active, first, count, level, passes, mats); break;
+      case 0 * 8 + 4: launch_xk<4, 0>(tm, blocks, st, circs, active, first, count, level, passes, mats); break;
+      case 1 * 8 + 1: launch_xk<1, 1>(tm, blocks, st, circs, active, first, count, level, passes, mats); break;
+      case 1 * 8 + 2: launch_xk<2, 1>(tm, blocks, st, circs, active, first, count, level, passes, mats); break;
+      case 1 * 8 + 3: launch_xk<3, 1>(tm, blocks, st, circs, active, first, count, level, passes, mats); break;
+      default: throw DeviceError{hipErrorInvalidValue, "batch: unsupported exchange shape"};
+    }
+    SV_HIP(hipGetLastError());
+    return;
+  }
+  shape = sh;
 #define SV_LEVEL(K_, M_)                                                                                     \
   case M_ * 8 + K_:                                                                                          \
     hipLaunchKernelGGL((k_batch_level<K_, M_>), dim3(blocks), dim3(256), 0, st, circs, active, first, count, \
@@ -169,6 +263,7 @@ void launch_level(int shape, unsigned blocks, hipStream_t st, const BCirc* circs
 std::mutex g_batch_mu;
 int g_lds_max_n = 12;  // largest LDS-resident state (qubits); set by the autotuner
 constexpr int kBatchLdsMaxQubits = 14;
+constexpr int kBatchExchangeMinQubits = 18;
 
 void fill_pass(BPass& bp, int n, const FusedGate& f, uint32_t mat) {
   int pos[SV_MAX_K];
@@ -193,6 +288,15 @@ void fill_pass(BPass& bp, int n, const FusedGate& f, uint32_t mat) {
     bp.stride[j] = j < bp.K ? (uint64_t)1 << pos[j] : 0;
   }
   bp.mat = mat;
+  // Passes with targets on element bits 0..2 of circuits of at least
+  // kBatchExchangeMinQubits qubits take the lane-exchange level kernel; on
+  // smaller states the extra launch per level costs more than the partial
+  // lines (the L2 completes them).
+  bp.tm = 0;
+  if (n >= kBatchExchangeMinQubits && ((bp.mode == 0 && bp.K <= 4) || (bp.mode == 1 && bp.K >= 1 && bp.K <= 3)) &&
+      bp.items % 64 == 0)
+    for (int j = 0; j < bp.K; ++j)
+      if (pos[j] <= 2) bp.tm |= 1 << pos[j];
 }
 
 }  // namespace
@@ -299,7 +403,7 @@ void batch_run_impl(void* const* psis, const int* ns, const sv_gate* const* circ
       if (ns[c] <= lds_n || circs[c].npass <= L) continue;
       const BPass& bp = passes[circs[c].pass0 + L];
       if (!shape_supported(bp.mode, bp.K)) throw std::invalid_argument("sv_batch_run: unsupported pass shape");
-      const int sh = bp.mode * 8 + bp.K;
+      const int sh = bp.tm * 24 + bp.mode * 8 + bp.K;
       if (slot[sh] < 0) {
         slot[sh] = (int)launch_list.size();
         launch_list.push_back(Launch{L, sh, {}, {}});

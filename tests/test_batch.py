@@ -134,3 +134,32 @@ def test_batch512_every_circuit_against_oracle_projections(max_k, fusion):
     finally:
         for s in states:
             s.free()
+
+
+def test_batch_lane_exchange_every_low_target_set():
+    """Circuits of 18 and 19 qubits (at and above the size from which the
+    batched level passes exchange across lanes), one per target set: every
+    set of low targets on amplitude bits 1..3 with k = 1..4 and, with bit 0
+    as a further target, k = 2..4; each circuit starts with a layer of random
+    one-qubit gates so that the state is dense, then the gate on the set.
+    Every circuit against the oracle."""
+    rng = np.random.Generator(np.random.PCG64(2024))
+    ns, circs = [], []
+    for q0 in (False, True):
+        for tm in range(1, 8):
+            lows = [t + 1 for t in range(3) if (tm >> t) & 1]
+            for k in range(1, 5):
+                if len(lows) + q0 > k:
+                    continue
+                n = 18 + (len(circs) % 2)
+                rest = [q for q in range(4, n) if q not in lows]
+                qs = lows + ([0] if q0 else []) + [int(q) for q in rng.choice(rest, k - len(lows) - q0, replace=False)]
+                rng.shuffle(qs)
+                layer = [C.Gate((q,), C.haar_unitary(1, rng)) for q in range(n)]
+                ns.append(n)
+                circs.append(layer + [C.Gate(tuple(qs), C.haar_unitary(k, rng))])
+    out, stats = run_batch(ns, circs, max_k=4, fusion="none")
+    print("circuits", len(ns), "passes", stats["passes"], "launches", stats["launches"], flush=True)
+    for n, c, got in zip(ns, circs, out):
+        r = oracle.compare(got, oracle.apply_circuit(n, c))
+        assert r["max_abs"] <= 1e-5 and r["infidelity"] <= 1e-6, ([g.qubits for g in c[-1:]], r)

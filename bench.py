@@ -340,7 +340,7 @@ def batch_figures(max_k: int) -> dict:
 def profile_workload(name: str, tune_qubits: int) -> None:
     """One 32-qubit workload of other_workloads() (or the 30-qubit grid at a
     small greedy max k, whose passes are all k <= 3, or the 512-circuit
-    batch), after the autotuner, run twice (the second run is the one to
+    batch, or the state reads at 32 qubits), after the autotuner, run twice (the second run is the one to
     read in a kernel trace).  It starts
     with a copy of known size (8 GiB read, 8 GiB written) that calibrates
     the HBM byte counters of rocprofv3 --pmc runs."""
@@ -360,6 +360,15 @@ def profile_workload(name: str, tune_qubits: int) -> None:
     torch.cuda.empty_cache()
     if name == "batch512":  # the batched workload (its own warm-up run first)
         log("batch512:", batch_figures(4))
+        return
+    if name == "reads32":  # the state reads, each twice, on a 32-qubit entangled state
+        st = sv.State(32)
+        try:
+            st.apply_circuit(C.grid_circuit(4, 8, 4, seed=0), max_k=5, fusion="greedy", precision="fp16x3")
+            for rep in range(2):
+                log("reads32 run %d:" % rep, state_reads(st, 32, reps=1))
+        finally:
+            st.free()
         return
     n = 32
     init = 0
@@ -387,6 +396,41 @@ def profile_workload(name: str, tune_qubits: int) -> None:
                                                                 for v in range(1, 5) if s["variant_passes"][v]}))
     finally:
         st.free()
+
+
+def state_reads(st, n: int, reps: int = 3) -> dict:
+    """Wall time of the synchronous state reads on an n-qubit state: one
+    Pauli term, 8 terms sharing a flip mask (quads of elements), 8 terms
+    with f = 1 (pairs inside an element), 8 diagonal terms, the marginal
+    over 10 qubits and 100k inverse-CDF samples."""
+    import numpy as np
+    import torch
+    import circuits as C
+    state_bytes = 8.0 * (1 << n)
+
+    def timed(fn, r=reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(r):
+            fn()
+        return (time.perf_counter() - t0) / r
+
+    out = {}
+    zm = np.array([(1 << t) | (1 << (t + 9)) for t in range(8)], dtype=np.uint64)
+    cases = (("pauli_1_term", np.array([0b101 << 20], np.uint64), np.array([0b11], np.uint64)),
+             ("pauli_8_terms_one_sweep", np.array([0b1011 << 20] * 8, dtype=np.uint64), zm),
+             ("pauli_8_terms_flip_bit_0", np.ones(8, np.uint64), zm),
+             ("pauli_8_diagonal_terms", np.zeros(8, np.uint64), zm))
+    for name, xm, z in cases:
+        t = timed(lambda: st.expect_pauli(xm, z))
+        out[name] = {"s": t, "GBps": state_bytes / t / 1e9}
+    t = timed(lambda: st.marginal_probs(tuple(range(0, 30, 3))))
+    out["marginal_10_qubits"] = {"s": t, "GBps": state_bytes / t / 1e9}
+    u = C.uniforms(100000, 0)
+    t = timed(lambda: st.sample(u), r=2)
+    out["sample_100k_shots"] = {"s": t, "shots_per_s": u.size / t}
+    return out
 
 
 def other_workloads() -> dict:
@@ -462,27 +506,7 @@ def other_workloads() -> dict:
                                      "alg_hbm_frac": s["bytes"] / s["gpu_s"] / 1e9 / HBM_PEAK_GBPS}
             log("qv32 %s:" % fusion, out["qv32_" + fusion])
         # state reads on the quantum-volume output
-        state_bytes = 8.0 * (1 << n)
-
-        def timed(fn, reps=3):
-            fn()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                fn()
-            return (time.perf_counter() - t0) / reps
-
-        xm = np.array([0b1011 << 20] * 8, dtype=np.uint64)
-        zm = np.array([(1 << t) | (1 << (t + 9)) for t in range(8)], dtype=np.uint64)
-        t = timed(lambda: st.expect_pauli(xm, zm))
-        out["pauli_8_terms_one_sweep"] = {"s": t, "GBps": state_bytes / t / 1e9}
-        t = timed(lambda: st.expect_pauli(np.zeros(8, np.uint64), zm))
-        out["pauli_8_diagonal_terms"] = {"s": t, "GBps": state_bytes / t / 1e9}
-        t = timed(lambda: st.marginal_probs(tuple(range(0, 30, 3))))
-        out["marginal_10_qubits"] = {"s": t, "GBps": state_bytes / t / 1e9}
-        u = C.uniforms(100000, 0)
-        t = timed(lambda: st.sample(u), reps=2)
-        out["sample_100k_shots"] = {"s": t, "shots_per_s": u.size / t}
+        out.update(state_reads(st, n))
         log("reads:", {k: out[k] for k in out if k.startswith(("pauli", "marginal", "sample"))})
     finally:
         st.free()
@@ -513,7 +537,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-workload", default=None,
                     choices=["qft32_greedy", "qft32_phase", "grover32", "qv32_greedy", "qv32_learned",
-                             "grid30_greedy2", "grid30_greedy3", "batch512"],
+                             "grid30_greedy2", "grid30_greedy3", "batch512", "reads32"],
                     help="autotune, then run one 30/32-qubit workload twice (or the 512-circuit batch) and exit "
                          "(for rocprofv3 runs)")
     ap.add_argument("--profile-step", action="store_true",

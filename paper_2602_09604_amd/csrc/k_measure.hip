@@ -24,8 +24,6 @@ __device__ __forceinline__ double sq(const float2 a) {
   return (double)a.x * (double)a.x + (double)a.y * (double)a.y;
 }
 
-__device__ __forceinline__ double parity_sign(uint64_t x) { return (__popcll(x) & 1) ? -1.0 : 1.0; }
-
 // ------------------------------------------------------------ Pauli strings
 // Up to kTerms strings that share the flip mask f = X|Y part.  For P = i^ny
 // X^f Z^z: <psi|P|psi> = i^ny sum_i (-1)^{|(i^f) & z|} conj(c_i) c_{i^f}.
@@ -33,93 +31,125 @@ __device__ __forceinline__ double parity_sign(uint64_t x) { return (__popcll(x) 
 // bit of f) clear in i; the pair contributes s_i w + s_j conj(w), w =
 // conj(c_i) c_j, s_j = (-1)^{|i & z|} and s_i = s_j (-1)^{|f & z|}.  So a
 // term with |f & z| even collects 2 s_j Re w (a real sum) and one with
-// |f & z| odd collects -2i s_j Im w; each term needs one parity per pair.
-// Each amplitude is read once.
+// |f & z| odd collects -2i s_j Im w.  Each amplitude is read once.
 constexpr int kTerms = 8;
 struct PauliArgs {
   uint64_t f;
-  uint64_t items;          // float4 elements (f == 0 or f == 1) or element quads
+  uint64_t items;          // float4 elements (f == 0 or f == 1) or element quads; a power of two
   uint64_t lowmask;        // ones below bit h
   uint64_t z[kTerms];
+  uint32_t chi[kTerms][4]; // high words of the FP64 coefficients (+-1 or 0) of each item value
   uint32_t odd;            // bit t: |f & z_t| is odd
-  int nt;
-  int mode;                // 0: diagonal (f == 0); 1: f == 1; 2: h >= 1
 };
 
-__device__ __forceinline__ double signed_by(uint64_t x, double v) { return (__popcll(x) & 1) ? -v : v; }
-
-// Amplitudes i (even) and i + 1 of one element: their signs differ exactly
-// when z has bit 0 set.
-__device__ __forceinline__ void diag_add(double* acc, const PauliArgs& a, uint64_t i, const float4 v) {
-  const double p0 = sq(make_float2(v.x, v.y)), p1 = sq(make_float2(v.z, v.w));
-  const double same = p0 + p1, diff = p0 - p1;
-#pragma unroll
-  for (int t = 0; t < kTerms; ++t)
-    if (t < a.nt) acc[t] += signed_by(i & a.z[t], (a.z[t] & 1) ? diff : same);
+// First amplitude index of item x: 2x for elements; for quads, 2x with a
+// zero inserted at bit h (the bit-h-clear member of the pair).
+template <int MODE>
+__device__ __forceinline__ uint64_t first_amp(const PauliArgs& a, uint64_t x) {
+  const uint64_t g = 2 * x;
+  return MODE == 2 ? ((g & ~a.lowmask) << 1) | (g & a.lowmask) : g;
 }
 
-// Pair (i, i ^ f), i with bit h clear.
-__device__ __forceinline__ void pair_add(double* acc, const PauliArgs& a, uint64_t i, const float2 ci,
-                                         const float2 cj) {
-  const double wr = (double)ci.x * cj.x + (double)ci.y * cj.y;
-  const double wi = (double)ci.x * cj.y - (double)ci.y * cj.x;
+__device__ __forceinline__ uint32_t sign_bits(const PauliArgs& a, uint64_t i, int terms) {
+  uint32_t s = 0;
 #pragma unroll
   for (int t = 0; t < kTerms; ++t)
-    if (t < a.nt) acc[t] += signed_by(i & a.z[t], ((a.odd >> t) & 1) ? wi : wr);
+    if (t < terms) s |= (uint32_t)(__popcll(i & a.z[t]) & 1) << t;
+  return s;
 }
 
-// Block b owns a contiguous slice of items; every thread keeps two items in
-// flight.  Mode 0 and 1 items are float4 elements (amplitudes 2e, 2e + 1);
-// mode 2 items are quads: the element at i (bit h clear, i even) and the
-// element holding its partners i ^ f and (i + 1) ^ f.
-template <bool NT>
+__device__ __forceinline__ double coef(uint32_t hi, uint32_t sign) {
+  return __longlong_as_double((long long)((uint64_t)(hi ^ (sign << 31)) << 32));
+}
+
+// The values an item contributes, before signs: MODE 0, the two Born
+// probabilities |c_i|^2, |c_{i+1}|^2; MODE 1, Re and Im of w = conj(c_i)
+// c_{i+1}; MODE 2, Re and Im of w for the pairs at i and i + 1.
+template <int MODE>
+__device__ __forceinline__ void item_values(const float4 A, const float4 B, bool fodd, double* v) {
+  if (MODE == 0) {
+    v[0] = sq(make_float2(A.x, A.y));
+    v[1] = sq(make_float2(A.z, A.w));
+  } else if (MODE == 1) {
+    v[0] = (double)A.x * A.z + (double)A.y * A.w;
+    v[1] = (double)A.x * A.w - (double)A.y * A.z;
+  } else {
+    const float2 c0 = make_float2(A.x, A.y), c1 = make_float2(A.z, A.w);
+    const float2 p0 = fodd ? make_float2(B.z, B.w) : make_float2(B.x, B.y);
+    const float2 p1 = fodd ? make_float2(B.x, B.y) : make_float2(B.z, B.w);
+    v[0] = (double)c0.x * p0.x + (double)c0.y * p0.y;
+    v[1] = (double)c0.x * p0.y - (double)c0.y * p0.x;
+    v[2] = (double)c1.x * p1.x + (double)c1.y * p1.y;
+    v[3] = (double)c1.x * p1.y - (double)c1.y * p1.x;
+  }
+}
+
+template <int MODE, int TERMS>
+__device__ __forceinline__ void accumulate(double* acc, const PauliArgs& a, uint32_t sig, const double* v) {
+  constexpr int NV = MODE == 2 ? 4 : 2;
+#pragma unroll
+  for (int t = 0; t < TERMS; ++t) {
+    const uint32_t s = (sig >> t) & 1u;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) acc[t] = fma(coef(a.chi[t][c], s), v[c], acc[t]);
+  }
+}
+
+// Thread T of the grid (nth = gridDim.x * kThreads threads, a power of two)
+// owns items x = T + m nth, m = 0, 1, ...  The bits of first_amp(T) and
+// first_amp(m nth) are disjoint, so the sign (-1)^{|i & z_t|} of every pair
+// splits into a per-thread sign and a per-m sign that is the same for every
+// lane: the loop multiplies each value by wave-uniform coefficients (+-1 or
+// 0, the +-1 of bit 0 of z_t and the real-or-imaginary choice folded in) and
+// the thread applies its own signs once at the end.  Mode 0 and 1 items are
+// float4 elements (amplitudes 2x, 2x + 1); mode 2 items are quads: the
+// element at i (bit h clear, i even) and the element holding its partners
+// i ^ f and (i + 1) ^ f.  Every thread keeps two items in flight.
+template <bool NT, int MODE, int TERMS>
 __global__ __launch_bounds__(kThreads) void k_pauli_partial(const float4* __restrict__ psi, const PauliArgs a,
                                                            double* __restrict__ partials) {
+  constexpr int NV = MODE == 2 ? 4 : 2;
   double acc[kTerms];
 #pragma unroll
   for (int t = 0; t < kTerms; ++t) acc[t] = 0.0;
-  const uint64_t per = (a.items + gridDim.x - 1) / gridDim.x;
-  const uint64_t lo = (uint64_t)blockIdx.x * per;
-  const uint64_t hi = lo + per < a.items ? lo + per : a.items;
-  for (uint64_t x0 = lo + threadIdx.x; x0 < hi; x0 += 2 * kThreads) {
-    const uint64_t x1 = x0 + kThreads;
-    const bool has1 = x1 < hi;
-    if (a.mode == 0) {
-      const float4 v0 = gld<NT>(psi + x0);
-      const float4 v1 = has1 ? gld<NT>(psi + x1) : make_float4(0.f, 0.f, 0.f, 0.f);
-      diag_add(acc, a, 2 * x0, v0);
-      if (has1) diag_add(acc, a, 2 * x1, v1);
-    } else if (a.mode == 1) {
-      const float4 v0 = gld<NT>(psi + x0);
-      const float4 v1 = has1 ? gld<NT>(psi + x1) : make_float4(0.f, 0.f, 0.f, 0.f);
-      pair_add(acc, a, 2 * x0, make_float2(v0.x, v0.y), make_float2(v0.z, v0.w));
-      if (has1) pair_add(acc, a, 2 * x1, make_float2(v1.x, v1.y), make_float2(v1.z, v1.w));
-    } else {
-      const uint64_t g0 = 2 * x0, g1 = 2 * x1;
-      const uint64_t i0 = ((g0 & ~a.lowmask) << 1) | (g0 & a.lowmask);
-      const uint64_t i1 = ((g1 & ~a.lowmask) << 1) | (g1 & a.lowmask);
-      const uint64_t j0 = (i0 ^ a.f) & ~(uint64_t)1, j1 = (i1 ^ a.f) & ~(uint64_t)1;
-      const float4 A0 = gld<NT>(psi + (i0 >> 1)), B0 = gld<NT>(psi + (j0 >> 1));
-      float4 A1 = make_float4(0.f, 0.f, 0.f, 0.f), B1 = A1;
-      if (has1) {
-        A1 = gld<NT>(psi + (i1 >> 1));
-        B1 = gld<NT>(psi + (j1 >> 1));
+  const uint64_t nth = (uint64_t)gridDim.x * kThreads;
+  const uint64_t T = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+  const uint64_t iT = first_amp<MODE>(a, T);
+  const uint64_t i_step = first_amp<MODE>(a, nth);
+  const uint32_t step = sign_bits(a, i_step, TERMS);  // m even: m + 1 flips these
+  const bool fodd = a.f & 1;  // the partner of i is the odd amplitude of its element
+  if (T < a.items) {  // false only past the end of a state of fewer than nth items
+    // the trip count and has1 are the same for every lane, so the four
+    // loads of an iteration issue back to back (a lone last item loads
+    // its own element twice)
+    const uint64_t M = a.items >= nth ? a.items / nth : 1;
+    for (uint64_t m = 0; m < M; m += 2) {
+      const bool has1 = m + 1 < M;
+      const uint64_t im = first_amp<MODE>(a, m * nth);
+      const uint64_t i0 = iT | im, i1 = has1 ? i0 | i_step : i0;
+      const float4 A0 = gld<NT>(psi + (i0 >> 1));
+      const float4 A1 = gld<NT>(psi + (i1 >> 1));
+      float4 B0 = A0, B1 = A1;
+      if (MODE == 2) {
+        B0 = gld<NT>(psi + (((i0 ^ a.f) & ~(uint64_t)1) >> 1));
+        B1 = gld<NT>(psi + (((i1 ^ a.f) & ~(uint64_t)1) >> 1));
       }
-      const bool odd = a.f & 1;  // the partner of i is the odd amplitude of its element
-      pair_add(acc, a, i0, make_float2(A0.x, A0.y), odd ? make_float2(B0.z, B0.w) : make_float2(B0.x, B0.y));
-      pair_add(acc, a, i0 + 1, make_float2(A0.z, A0.w), odd ? make_float2(B0.x, B0.y) : make_float2(B0.z, B0.w));
+      const uint32_t sig = sign_bits(a, im, TERMS);
+      double v[NV];
+      item_values<MODE>(A0, B0, fodd, v);
+      accumulate<MODE, TERMS>(acc, a, sig, v);
       if (has1) {
-        pair_add(acc, a, i1, make_float2(A1.x, A1.y), odd ? make_float2(B1.z, B1.w) : make_float2(B1.x, B1.y));
-        pair_add(acc, a, i1 + 1, make_float2(A1.z, A1.w),
-                 odd ? make_float2(B1.x, B1.y) : make_float2(B1.z, B1.w));
+        item_values<MODE>(A1, B1, fodd, v);
+        accumulate<MODE, TERMS>(acc, a, sig ^ step, v);
       }
     }
   }
+  const uint32_t own = sign_bits(a, iT, TERMS);
   __shared__ double part[kThreads / 64][kTerms];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
   for (int t = 0; t < kTerms; ++t) {
-    const double r = wave_sum(acc[t]);
+    const double r = wave_sum(((own >> t) & 1) ? -acc[t] : acc[t]);
     if (lane == 0) part[w][t] = r;
   }
   __syncthreads();
@@ -130,19 +160,41 @@ __global__ __launch_bounds__(kThreads) void k_pauli_partial(const float4* __rest
   }
 }
 
-// Sum the per-block partials in block order and form S_t = sum_i
-// (-1)^{|(i^f) & z_t|} conj(c_i) c_{i^f}: out[2t], out[2t+1] = Re, Im (the
-// i^ny factor is applied on the host).
-__global__ __launch_bounds__(64) void k_pauli_final(const double* __restrict__ partials, int blocks, int mode,
-                                                   uint32_t odd, double* __restrict__ out) {
-  const int t = threadIdx.x;
-  if (t >= kTerms) return;
+// Column sums of the blocks x width matrix of per-block partials, in a fixed
+// order: workgroup g owns columns 64 g .. 64 g + 63 (one per lane); each of
+// its 16 waves sums a contiguous run of rows, and wave 0 then adds the 16
+// wave sums in wave order.  With PAULI the column sums S_t become
+// out[2t], out[2t + 1] = Re, Im of sum_i (-1)^{|(i^f) & z_t|} conj(c_i)
+// c_{i^f} (the i^ny factor is applied on the host); otherwise out[col] is
+// the sum itself.
+constexpr int kFinalWaves = 16;
+template <bool PAULI>
+__global__ __launch_bounds__(64 * kFinalWaves) void k_column_sums(const double* __restrict__ partials, int blocks,
+                                                                  int width, int mode, uint32_t odd,
+                                                                  double* __restrict__ out) {
+  __shared__ double part[kFinalWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int col = blockIdx.x * 64 + lane;
+  const int per = (blocks + kFinalWaves - 1) / kFinalWaves;
+  const int b0 = w * per, b1 = b0 + per < blocks ? b0 + per : blocks;
   double s = 0.0;
-  for (int b = 0; b < blocks; ++b) s += partials[(size_t)b * kTerms + t];
-  const double scale = mode == 0 ? 1.0 : 2.0;
-  const bool is_odd = (odd >> t) & 1;
-  out[2 * t] = is_odd ? 0.0 : scale * s;
-  out[2 * t + 1] = is_odd ? -scale * s : 0.0;
+  if (col < width) {
+#pragma unroll 8
+    for (int b = b0; b < b1; ++b) s += partials[(size_t)b * width + col];
+  }
+  part[w][lane] = s;
+  __syncthreads();
+  if (w != 0 || col >= width) return;
+  double t = 0.0;
+  for (int x = 0; x < kFinalWaves; ++x) t += part[x][lane];
+  if (PAULI) {
+    const double scale = mode == 0 ? 1.0 : 2.0;
+    const bool is_odd = (odd >> col) & 1;
+    out[2 * col] = is_odd ? 0.0 : scale * t;
+    out[2 * col + 1] = is_odd ? -scale * t : 0.0;
+  } else {
+    out[col] = t;
+  }
 }
 
 // ------------------------------------------------------- marginal probabilities
@@ -236,15 +288,6 @@ __global__ __launch_bounds__(kThreads) void k_marginal_partial(const float2* __r
     for (int x = 0; x < 4; ++x) v += hist[x * M + o];
     partials[(size_t)blockIdx.x * M + o] = v;
   }
-}
-
-__global__ __launch_bounds__(kThreads) void k_marginal_final(const double* __restrict__ partials, int blocks, int M,
-                                                            double* __restrict__ out) {
-  const int o = blockIdx.x * kThreads + threadIdx.x;
-  if (o >= M) return;
-  double s = 0.0;
-  for (int b = 0; b < blocks; ++b) s += partials[(size_t)b * M + o];
-  out[o] = s;
 }
 
 // ------------------------------------------------------------------ sampling
@@ -387,28 +430,60 @@ void launch_pauli(const void* psi, int n, uint64_t f, int nt, const uint64_t* z,
   if (nt < 1 || nt > kTerms) throw DeviceError{hipErrorInvalidValue, "k_pauli: 1..8 terms per sweep"};
   PauliArgs a{};
   a.f = f;
-  a.nt = nt;
   for (int t = 0; t < nt; ++t) {
     a.z[t] = z[t];
     if (__builtin_popcountll(f & z[t]) & 1) a.odd |= 1u << t;
   }
   if (n < 1 || (n < 64 && (f >> n) != 0)) throw DeviceError{hipErrorInvalidValue, "k_pauli: flip mask past n"};
+  int mode;
   if (f == 0 || f == 1) {
-    a.mode = (int)f;
+    mode = (int)f;
     a.items = (uint64_t)1 << (n - 1);  // n = 1: one element
   } else {
     const int h = 63 - __builtin_clzll(f);  // h >= 1, so n >= 2
-    a.mode = 2;
+    mode = 2;
     a.lowmask = ((uint64_t)1 << h) - 1;
     a.items = (uint64_t)1 << (n - 2);
   }
-  const unsigned blocks = blocks_for(a.items, 2);
-  if (n >= kern::kNtMinQubits)
-    hipLaunchKernelGGL(k_pauli_partial<true>, dim3(blocks), dim3(kThreads), 0, st, (const float4*)psi, a, scratch);
-  else
-    hipLaunchKernelGGL(k_pauli_partial<false>, dim3(blocks), dim3(kThreads), 0, st, (const float4*)psi, a, scratch);
-  hipLaunchKernelGGL(k_pauli_final, dim3(1), dim3(64), 0, st, (const double*)scratch, (int)blocks, a.mode, a.odd,
-                     out);
+  // coefficients of the item values: mode 0 (|c_i|^2, |c_{i+1}|^2) with the
+  // sign of z_t bit 0 on the second; modes 1, 2: Re w for an even |f & z_t|,
+  // Im w for an odd one, and in mode 2 the pair at i + 1 again signed by bit 0
+  constexpr uint32_t kOne = 0x3FF00000u, kNeg = 0x80000000u;
+  for (int t = 0; t < nt; ++t) {
+    const uint32_t zeta = (z[t] & 1) ? kNeg : 0u;
+    const bool im = (a.odd >> t) & 1;
+    if (mode == 0) {
+      a.chi[t][0] = kOne;
+      a.chi[t][1] = kOne | zeta;
+    } else {
+      a.chi[t][0] = im ? 0u : kOne;
+      a.chi[t][1] = im ? kOne : 0u;
+      a.chi[t][2] = a.chi[t][0] ? a.chi[t][0] | zeta : 0u;
+      a.chi[t][3] = a.chi[t][1] ? a.chi[t][1] | zeta : 0u;
+    }
+  }
+  const unsigned blocks = blocks_for(a.items, 2);  // a power of two, as the kernel's split of signs needs
+  const int terms = nt <= 1 ? 1 : nt <= 2 ? 2 : nt <= 4 ? 4 : 8;
+  const bool nt_loads = n >= kern::kNtMinQubits;
+  using Kern = void (*)(const float4*, PauliArgs, double*);
+  static constexpr Kern table[2][3][4] = {
+      {{k_pauli_partial<false, 0, 1>, k_pauli_partial<false, 0, 2>, k_pauli_partial<false, 0, 4>,
+        k_pauli_partial<false, 0, 8>},
+       {k_pauli_partial<false, 1, 1>, k_pauli_partial<false, 1, 2>, k_pauli_partial<false, 1, 4>,
+        k_pauli_partial<false, 1, 8>},
+       {k_pauli_partial<false, 2, 1>, k_pauli_partial<false, 2, 2>, k_pauli_partial<false, 2, 4>,
+        k_pauli_partial<false, 2, 8>}},
+      {{k_pauli_partial<true, 0, 1>, k_pauli_partial<true, 0, 2>, k_pauli_partial<true, 0, 4>,
+        k_pauli_partial<true, 0, 8>},
+       {k_pauli_partial<true, 1, 1>, k_pauli_partial<true, 1, 2>, k_pauli_partial<true, 1, 4>,
+        k_pauli_partial<true, 1, 8>},
+       {k_pauli_partial<true, 2, 1>, k_pauli_partial<true, 2, 2>, k_pauli_partial<true, 2, 4>,
+        k_pauli_partial<true, 2, 8>}}};
+  const int ti = terms == 1 ? 0 : terms == 2 ? 1 : terms == 4 ? 2 : 3;
+  hipLaunchKernelGGL(table[nt_loads][mode][ti], dim3(blocks), dim3(kThreads), 0, st, (const float4*)psi, a,
+                     scratch);
+  hipLaunchKernelGGL(k_column_sums<true>, dim3(1), dim3(64 * kFinalWaves), 0, st, (const double*)scratch,
+                     (int)blocks, kTerms, mode, a.odd, out);
   SV_HIP(hipGetLastError());
 }
 
@@ -439,8 +514,8 @@ void launch_marginal(const void* psi, int n, int m, const int* qubits, double* s
   else
     hipLaunchKernelGGL(k_marginal_partial<false>, dim3(blocks), dim3(kThreads), sizeof(double) * 4 * M, st,
                        (const float2*)psi, a, scratch);
-  hipLaunchKernelGGL(k_marginal_final, dim3((M + kThreads - 1) / kThreads), dim3(kThreads), 0, st,
-                     (const double*)scratch, (int)blocks, M, out);
+  hipLaunchKernelGGL(k_column_sums<false>, dim3((M + 63) / 64), dim3(64 * kFinalWaves), 0, st,
+                     (const double*)scratch, (int)blocks, M, 0, 0u, out);
   SV_HIP(hipGetLastError());
 }
 

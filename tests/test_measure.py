@@ -56,6 +56,28 @@ def test_pauli_many_terms_one_flip_split_into_sweeps():
         st.free()
 
 
+@pytest.mark.parametrize("flip", [0, 1, 0b10, (1 << 22) | (1 << 3) | 1, (1 << 20) | 0b110, (1 << 21) | (1 << 9)])
+def test_pauli_long_walks_at_23_qubits(flip):
+    """At 23 qubits every thread of the sweep walks 4 to 8 items, so the part
+    of each term's sign that comes from the walk changes along it.  Per flip
+    mask: 8, 3 and 2 terms in one sweep, z masks with bits in the thread's
+    part, the walk's part (bits 20..22), bit 0 and the flip's own bits."""
+    n = 23
+    st, psi = load_state(n, 31)
+    try:
+        full = (1 << n) - 1
+        rng = np.random.Generator(np.random.PCG64(flip + 7))
+        z = [int(v) for v in rng.integers(0, 1 << n, size=8, dtype=np.uint64)]
+        z[0], z[1], z[2], z[3] = 0, (1 << 22) | (1 << 21) | (1 << 20), full, flip | 1
+        for count in (8, 3, 2):
+            zs = z[:count]
+            got = st.expect_pauli([flip] * count, zs)
+            ref = np.array([oracle.pauli_expectation(psi, n, flip, b).real for b in zs])
+            assert np.max(np.abs(got - ref)) < 1e-12, (count, np.max(np.abs(got - ref)))
+    finally:
+        st.free()
+
+
 def test_pauli_ghz_closed_forms_at_30_qubits():
     from paper_2602_09604_amd import sv
     n = 30

@@ -54,9 +54,10 @@ __global__ __launch_bounds__(256) void k_apply_reg(void* __restrict__ psi_,
 // the work item u(j) | c(j) << (6 - m) of the wave's 64 (c(j): j's bits in TM,
 // u(j): its other bits); load slot X reads, in lane j, the element of item
 // u(j) | X << (6 - m) whose low-target local bits are c(j), so that 8 aligned
-// lanes read one whole line; a butterfly over the m targets then hands every
-// lane all elements of its own item.  Outputs go back the same way, 2^m rows
-// at a time.  The number of work items is a multiple of 64.
+// lanes read one whole line; a butterfly over the m targets (m = 1) or a
+// transpose through LDS (m = 2, 3) then hands every lane all elements of its
+// own item.  Outputs go back the same way, 2^m rows at a time.  The number of
+// work items is a multiple of 64.
 template <int K, int MODE, int TM>
 __global__ __launch_bounds__(256) void k_apply_reg_x(float4* __restrict__ psi, const float2* __restrict__ U,
                                                      const RegArgs<uint64_t> a) {
@@ -79,13 +80,17 @@ __global__ __launch_bounds__(256) void k_apply_reg_x(float4* __restrict__ psi, c
   float4 v[D];
 #pragma unroll
   for (int r = 0; r < D; ++r) v[r] = gld<true>(psi + b0 + xoff[r & XM] + local_offset<K, uint64_t>(r & ~XM, a.stride));
-  xtranspose<TM>(v, j);
+  __shared__ float4 xs[M >= 2 ? 4 * D * 64 : 1];  // the LDS hand-over of m = 2, 3
+  float4* t = xs + (M >= 2 ? (threadIdx.x >> 6) * D * 64 : 0);
+  if constexpr (M >= 2) xtranspose_lds<TM>(v, t, j, cj);
+  else xtranspose<TM>(v, j);
 #pragma unroll
   for (int hi = 0; hi < D; hi += XM + 1) {
     float4 o[XM + 1];
 #pragma unroll
     for (int x = 0; x <= XM; ++x) o[x] = pair_row<K, MODE>(v, U, hi | x);
-    xtranspose<TM>(o, j);
+    if constexpr (M >= 2) xtranspose_lds_back<TM>(o, t, hi, j, cj);
+    else xtranspose<TM>(o, j);
 #pragma unroll
     for (int x = 0; x <= XM; ++x) gst<true>(psi + b0 + xoff[x] + local_offset<K, uint64_t>(hi, a.stride), o[x]);
   }

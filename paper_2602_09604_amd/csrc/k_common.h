@@ -147,6 +147,50 @@ __device__ __forceinline__ void xtranspose(float4 (&R)[N], int j) {
   if constexpr (M >= 3) xstage<TM, 2, N>(R, j);
 }
 
+// the low bits of x placed at the positions of the set bits of TM, ascending
+template <int TM>
+__host__ __device__ constexpr int spread_bits(int x) {
+  int o = 0, c = 0;
+  for (int b = 0; b < 3; ++b)
+    if ((TM >> b) & 1) o |= ((x >> c++) & 1) << b;
+  return o;
+}
+
+// orders the LDS accesses of one wavefront around it (lanes of a wave
+// exchange data through LDS without a workgroup barrier)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The same hand-over through LDS, for m = 2 or 3, where the butterfly's
+// stages cost more lane swaps and selects than a trip through LDS.  t holds
+// N * 64 float4 per wavefront.  Register r goes to row r, column
+// j ^ spread(r & XM); lane j then reads row (r & ~XM) | c(j) at the same
+// column.  The XOR keeps the writes and the reads free of bank conflicts.
+template <int TM, int N>
+__device__ __forceinline__ void xtranspose_lds(float4 (&R)[N], float4* t, int j, int cj) {
+  constexpr int XM = (1 << LowBits<TM>::m) - 1;
+#pragma unroll
+  for (int r = 0; r < N; ++r) t[r * 64 + (j ^ spread_bits<TM>(r & XM))] = R[r];
+  wave_sync();
+#pragma unroll
+  for (int r = 0; r < N; ++r) R[r] = t[((r & ~XM) | cj) * 64 + (j ^ spread_bits<TM>(r & XM))];
+}
+
+// Its inverse for the 2^m outputs O[x] = row hb | x of this lane's own item
+// (hb a multiple of 2^m): afterwards O[X] is slot X's element, as loaded.
+template <int TM, int N>
+__device__ __forceinline__ void xtranspose_lds_back(float4 (&O)[N], float4* t, int hb, int j, int cj) {
+  wave_sync();  // every lane has read what these writes replace
+#pragma unroll
+  for (int x = 0; x < N; ++x) t[(hb | cj) * 64 + (j ^ spread_bits<TM>(x))] = O[x];
+  wave_sync();
+#pragma unroll
+  for (int x = 0; x < N; ++x) O[x] = t[(hb | x) * 64 + (j ^ spread_bits<TM>(x))];
+}
+
 // bits of v at the positions of mask (BITS-bit values), packed ascending
 template <int BITS>
 __device__ __forceinline__ int compress_bits(int v, int mask) {

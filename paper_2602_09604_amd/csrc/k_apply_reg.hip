@@ -44,8 +44,21 @@ __global__ __launch_bounds__(256) void k_apply_reg(void* __restrict__ psi_,
     float4 v[D];
 #pragma unroll
     for (int l = 0; l < D; ++l) v[l] = gld<NT>(psi + base + local_offset<K, IDX>(l, a.stride));
+    if constexpr (K <= 4) {
+      // the 3M row products: up to K = 4 the extra input sums and third
+      // accumulator still leave room for several waves per SIMD; at K = 5
+      // they would leave one (measured slower than the 4M form)
+      const float* __restrict__ U3 = u3_of<K, MODE>(U);
+      float2 sv[D];
+      input_sums<D>(v, sv);
 #pragma unroll
-    for (int r = 0; r < D; ++r) gst<NT>(psi + base + local_offset<K, IDX>(r, a.stride), pair_row<K, MODE>(v, U, r));
+      for (int r = 0; r < D; ++r)
+        gst<NT>(psi + base + local_offset<K, IDX>(r, a.stride), pair_row3<K, MODE>(v, sv, U3, r));
+    } else {
+#pragma unroll
+      for (int r = 0; r < D; ++r)
+        gst<NT>(psi + base + local_offset<K, IDX>(r, a.stride), pair_row<K, MODE>(v, U, r));
+    }
   }
 }
 

@@ -255,5 +255,66 @@ __device__ __forceinline__ float4 pair_row(const float4* v, const float2* __rest
   return make_float4(a0.x, a0.y, a1.x, a1.y);
 }
 
+// The 3M form of the same row products (three real products per complex
+// multiply-accumulate instead of four), for the register kernel, whose
+// larger passes are bound by the vector ALUs.  With s = vr + vi per input
+// and the matrix stored as u3 = (ur, ur + ui, ui - ur) per element:
+// T += ur s, R += vi (ur + ui), I += vr (ui - ur); then Re = T - R and
+// Im = T + I (T - R = sum ur vr - ui vi, T + I = sum ur vi + ui vr).
+struct Acc3 {
+  float t = 0.f, r = 0.f, i = 0.f;
+};
+
+__device__ __forceinline__ void cmac3(Acc3& a, const float* __restrict__ u3, const float vr, const float vi,
+                                      const float s) {
+  a.t = fmaf(u3[0], s, a.t);
+  a.r = fmaf(vi, u3[1], a.r);
+  a.i = fmaf(vr, u3[2], a.i);
+}
+
+__device__ __forceinline__ float2 fin3(const Acc3& a) { return make_float2(a.t - a.r, a.t + a.i); }
+
+// where the 3M copy starts in a register pass's data: after the d x d
+// complex64 matrix, d = 2^K (MODE 0, 2) or 2^(K+1) (MODE 1)
+template <int K, int MODE>
+__device__ __forceinline__ const float* u3_of(const float2* U) {
+  constexpr int d = MODE == 1 ? 2 << K : 1 << K;
+  return reinterpret_cast<const float*>(U + d * d);
+}
+
+// s = vr + vi of both amplitudes of every input element
+template <int D>
+__device__ __forceinline__ void input_sums(const float4* v, float2* s) {
+#pragma unroll
+  for (int c = 0; c < D; ++c) s[c] = make_float2(v[c].x + v[c].y, v[c].z + v[c].w);
+}
+
+// pair_row in the 3M form; s from input_sums
+template <int K, int MODE>
+__device__ __forceinline__ float4 pair_row3(const float4* v, const float2* s, const float* __restrict__ U3,
+                                            const int r) {
+  constexpr int D = 1 << K;
+  Acc3 a0, a1;
+  if constexpr (MODE == 0) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const float* u = U3 + 3 * (r * D + c);
+      cmac3(a0, u, v[c].x, v[c].y, s[c].x);
+      cmac3(a1, u, v[c].z, v[c].w, s[c].y);
+    }
+  } else {
+    constexpr int DM = 2 * D;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      cmac3(a0, U3 + 3 * ((2 * r) * DM + 2 * c), v[c].x, v[c].y, s[c].x);
+      cmac3(a0, U3 + 3 * ((2 * r) * DM + 2 * c + 1), v[c].z, v[c].w, s[c].y);
+      cmac3(a1, U3 + 3 * ((2 * r + 1) * DM + 2 * c), v[c].x, v[c].y, s[c].x);
+      cmac3(a1, U3 + 3 * ((2 * r + 1) * DM + 2 * c + 1), v[c].z, v[c].w, s[c].y);
+    }
+  }
+  const float2 o0 = fin3(a0), o1 = fin3(a1);
+  return make_float4(o0.x, o0.y, o1.x, o1.y);
+}
+
 }  // namespace kern
 }  // namespace sv

@@ -125,10 +125,10 @@ __device__ __forceinline__ void accumulate(double* acc, const PauliArgs& a, uint
 // lane; it reaches the sums through wave-uniform coefficients (+-1 or 0:
 // the real-or-imaginary choice and the sign of bit 0 of z_t folded in), in
 // one of the two ways described at accumulate, and the thread's own sign is
-// applied once at the end.  Mode 0 and 1 items are
-// float4 elements (amplitudes 2x, 2x + 1); mode 2 items are quads: the
-// element at i (bit h clear, i even) and the element holding its partners
-// i ^ f and (i + 1) ^ f.  Every thread keeps two items in flight.
+// applied once at the end.  Mode 0 and 1 items are float4 elements
+// (amplitudes 2x, 2x + 1); mode 2 items are quads: the element at i (bit h
+// clear, i even) and the element holding its partners i ^ f and
+// (i + 1) ^ f.  Every thread keeps two items in flight.
 template <bool NT, int MODE, int TERMS>
 __global__ __launch_bounds__(kThreads) void k_pauli_partial(const float4* __restrict__ psi, const PauliArgs a,
                                                            double* __restrict__ partials) {

@@ -108,3 +108,17 @@ def test_register_low_target_sets(setup, k, q0):
         r = run_and_check(st, psi0, ref0, [g], "fp32_valu", variant="reg")
         say("reg k=%d" % k, "targets", qs, r)
         assert r["max_abs"] <= MAX_ABS and r["infidelity"] <= INFID, (qs, r)
+
+
+@pytest.mark.parametrize("qs", [(6, 17), (5, 9, 14, 20), (0, 4, 9), (0, 5, 9, 14, 20), (20, 14, 0, 9, 5)])
+def test_register_streamed_3m_forms(setup, qs):
+    """The register kernel's 3M row products on a streamed state (no target
+    on amplitude bits 1..3, so the plain register form runs, non-temporal):
+    two and four element-space targets, without and with bit 0 as a target
+    (k = 5 with bit 0 is the largest 3M form)."""
+    st, psi0, ref0 = setup
+    rng = np.random.Generator(np.random.PCG64(sum(qs) + len(qs)))
+    g = C.Gate(qs, C.haar_unitary(len(qs), rng))
+    r = run_and_check(st, psi0, ref0, [g], "fp32_valu", variant="reg")
+    say("reg 3M targets", qs, r)
+    assert r["max_abs"] <= MAX_ABS and r["infidelity"] <= INFID, (qs, r)

@@ -47,7 +47,10 @@ extern "C" {
 /* ---- enumerations ------------------------------------------------------- */
 #define SV_C64 0              /* state dtype: complex64 (the only one built) */
 
-/* Arithmetic of a pass.  FP32_VALU: every pass on vector FP32 FMAs.
+/* Arithmetic of a pass.  FP32_VALU: every pass on vector FP32 FMAs
+ * (register passes with at most four targets besides bit 0 multiply in the
+ * 3M form, three real products per complex multiply-accumulate, with the
+ * matrix's ur + ui and ui - ur formed in FP64).
  * FP32_MFMA: passes with k >= 4 as a real GEMM in the 4M form
  * [Yr;Yi] = [[Ur,-Ui],[Ui,Ur]] [Xr;Xi] on FP32 matrix cores.
  * BF16X3 / FP16X3: the same GEMM with every operand split into hi + lo

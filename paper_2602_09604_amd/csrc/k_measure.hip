@@ -330,10 +330,17 @@ __global__ __launch_bounds__(kThreads) void k_chunk_sums(const float2* __restric
   const uint64_t ch = ((uint64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (ch >= nchunks) return;  // whole waves leave together
-  const uint64_t len = (uint64_t)1 << cbits;
-  const float2* __restrict__ p = psi + (ch << cbits);
+  // 16-byte loads (two amplitudes per lane), several in flight: the sum
+  // order per lane stays fixed (cbits >= 1, so a chunk is whole elements)
+  const uint64_t len4 = (uint64_t)1 << (cbits - 1);
+  const float4* __restrict__ p = reinterpret_cast<const float4*>(psi + (ch << cbits));
   double v = 0.0;
-  for (uint64_t i = lane; i < len; i += 64) v += sq(gld<NT>(p + i));
+#pragma unroll 8
+  for (uint64_t i = lane; i < len4; i += 64) {
+    const float4 a = gld<NT>(p + i);
+    v += sq(make_float2(a.x, a.y));
+    v += sq(make_float2(a.z, a.w));
+  }
   v = wave_sum(v);
   if (lane == 0) sums[ch] = v;
 }
@@ -564,6 +571,7 @@ size_t sample_scratch_bytes(int n) {
 void launch_sample(const void* psi, int n, bool prepare, const double* uniforms, uint64_t shots, uint64_t* out,
                    double* scratch, hipStream_t st) {
   const int c = sample_chunk_bits(n);
+  if (c < 1) throw DeviceError{hipErrorInvalidValue, "k_sample: a chunk must hold whole 16-byte elements"};
   const uint64_t nchunks = (uint64_t)1 << (n - c);
   double* incl = scratch;
   double* totals = scratch + nchunks;

@@ -91,6 +91,24 @@ def test_pauli_ghz_closed_forms_at_30_qubits():
         st.free()
 
 
+def test_pauli_ghz_closed_forms_at_33_qubits():
+    """Past 32 qubits (64-bit indices; every thread walks 8192 items): GHZ
+    closed forms with Z and Y letters on the top qubit, quads and diagonal
+    terms in one call."""
+    from paper_2602_09604_amd import sv
+    n = 33
+    st = sv.State(n)
+    try:
+        st.apply_circuit(C.ghz_circuit(n), max_k=4)
+        full = (1 << n) - 1
+        top = 1 << (n - 1)
+        got = st.expect_pauli([full, full, full, 0, 0, 0],
+                              [0, top | 1, top | 0b110, top | (1 << 7), top, 0])
+        assert np.allclose(got, [1, -1, 0, 1, 0, 1], atol=1e-5), got
+    finally:
+        st.free()
+
+
 @pytest.mark.parametrize("n,qs", [(1, (0,)), (4, (3, 0)), (8, (0, 1, 2, 3, 4, 5, 6, 7)), (12, (11, 0, 5)),
                                   (16, (6, 7, 8)), (18, (2, 17, 9, 0, 12)),
                                   (20, (19, 18, 1, 3, 5, 7, 9, 11, 13, 15))])

@@ -118,6 +118,24 @@ __device__ __forceinline__ void accumulate(double* acc, const PauliArgs& a, uint
   }
 }
 
+// Apply each thread's own signs (bit t of own), then sum the block's
+// threads in a fixed order into partials[block][t].
+__device__ __forceinline__ void block_partials(const double* acc, uint32_t own, double* __restrict__ partials) {
+  __shared__ double part[kThreads / 64][kTerms];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int t = 0; t < kTerms; ++t) {
+    const double r = wave_sum(((own >> t) & 1) ? -acc[t] : acc[t]);
+    if (lane == 0) part[w][t] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < kTerms) {
+    double v = 0.0;
+    for (int x = 0; x < kThreads / 64; ++x) v += part[x][threadIdx.x];
+    partials[(size_t)blockIdx.x * kTerms + threadIdx.x] = v;
+  }
+}
+
 // Thread T of the grid (nth = gridDim.x * kThreads threads, a power of two)
 // owns items x = T + m nth, m = 0, 1, ...  The bits of first_amp(T) and
 // first_amp(m nth) are disjoint, so the sign (-1)^{|i & z_t|} of every pair
@@ -172,19 +190,56 @@ __global__ __launch_bounds__(kThreads) void k_pauli_partial(const float4* __rest
     }
   }
   const uint32_t own = sign_bits(a, iT, TERMS) ^ (kFlips<MODE> ? last : 0u);
-  __shared__ double part[kThreads / 64][kTerms];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  block_partials(acc, own, partials);
+}
+
+// The same sums on a streamed state, walked the way the sampling chunk sums
+// walk it: wave W of NW takes chunks of R = 2048 consecutive items, W,
+// W + NW, W + 2 NW, ..., each in 32 steps of 64 lanes, two steps in flight
+// (so the waves in flight read a moving window of the state, each its own
+// 32 KiB run; the grid-stride walk above spreads every wave over the whole
+// state).  Item x = c NW R + W R + k 64 + lane splits into disjoint bit
+// fields, so the per-thread part of every sign comes from W R + lane and
+// the wave-uniform part from c NW R + k 64.  Needs items to be a multiple
+// of NW R.
+constexpr uint64_t kChunkItems = 2048;
+template <int MODE, int TERMS>
+__global__ __launch_bounds__(kThreads) void k_pauli_chunks(const float4* __restrict__ psi, const PauliArgs a,
+                                                          double* __restrict__ partials) {
+  constexpr int NV = MODE == 2 ? 4 : 2;
+  double acc[kTerms];
 #pragma unroll
-  for (int t = 0; t < kTerms; ++t) {
-    const double r = wave_sum(((own >> t) & 1) ? -acc[t] : acc[t]);
-    if (lane == 0) part[w][t] = r;
+  for (int t = 0; t < kTerms; ++t) acc[t] = 0.0;
+  const uint64_t NW = (uint64_t)gridDim.x * (kThreads / 64);
+  const uint64_t W = (uint64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const uint64_t iT = first_amp<MODE>(a, W * kChunkItems + lane);
+  const uint64_t rounds = a.items / (NW * kChunkItems);
+  const bool fodd = a.f & 1;
+  uint32_t last = 0;
+  for (uint64_t c = 0; c < rounds; ++c) {
+    for (uint64_t k = 0; k < kChunkItems / 64; k += 2) {
+      const uint64_t im0 = first_amp<MODE>(a, c * NW * kChunkItems + k * 64);
+      const uint64_t im1 = first_amp<MODE>(a, c * NW * kChunkItems + (k + 1) * 64);
+      const uint64_t i0 = iT | im0, i1 = iT | im1;
+      const float4 A0 = gld<true>(psi + (i0 >> 1));
+      const float4 A1 = gld<true>(psi + (i1 >> 1));
+      float4 B0 = A0, B1 = A1;
+      if (MODE == 2) {
+        B0 = gld<true>(psi + (((i0 ^ a.f) & ~(uint64_t)1) >> 1));
+        B1 = gld<true>(psi + (((i1 ^ a.f) & ~(uint64_t)1) >> 1));
+      }
+      const uint32_t sig0 = sign_bits(a, im0, TERMS), sig1 = sign_bits(a, im1, TERMS);
+      double v[NV];
+      item_values<MODE>(A0, B0, fodd, v);
+      accumulate<MODE, TERMS>(acc, a, kFlips<MODE> ? sig0 ^ last : sig0, v);
+      item_values<MODE>(A1, B1, fodd, v);
+      accumulate<MODE, TERMS>(acc, a, kFlips<MODE> ? sig1 ^ sig0 : sig1, v);
+      last = sig1;
+    }
   }
-  __syncthreads();
-  if (threadIdx.x < kTerms) {
-    double v = 0.0;
-    for (int x = 0; x < kThreads / 64; ++x) v += part[x][threadIdx.x];
-    partials[(size_t)blockIdx.x * kTerms + threadIdx.x] = v;
-  }
+  const uint32_t own = sign_bits(a, iT, TERMS) ^ (kFlips<MODE> ? last : 0u);
+  block_partials(acc, own, partials);
 }
 
 // Column sums of the blocks x width matrix of per-block partials, in a fixed
@@ -514,10 +569,21 @@ void launch_pauli(const void* psi, int n, uint64_t f, int nt, const uint64_t* z,
        {k_pauli_partial<true, 2, 1>, k_pauli_partial<true, 2, 2>, k_pauli_partial<true, 2, 4>,
         k_pauli_partial<true, 2, 8>}}};
   const int ti = terms == 1 ? 0 : terms == 2 ? 1 : terms == 4 ? 2 : 3;
-  hipLaunchKernelGGL(table[nt_loads][mode][ti], dim3(blocks), dim3(kThreads), 0, st, (const float4*)psi, a,
-                     scratch);
+  unsigned used = blocks;
+  const uint64_t chunk_waves = (uint64_t)kMaxBlocks * (kThreads / 64);
+  if (nt_loads && a.items % (chunk_waves * kChunkItems) == 0) {
+    static constexpr Kern chunks[3][4] = {
+        {k_pauli_chunks<0, 1>, k_pauli_chunks<0, 2>, k_pauli_chunks<0, 4>, k_pauli_chunks<0, 8>},
+        {k_pauli_chunks<1, 1>, k_pauli_chunks<1, 2>, k_pauli_chunks<1, 4>, k_pauli_chunks<1, 8>},
+        {k_pauli_chunks<2, 1>, k_pauli_chunks<2, 2>, k_pauli_chunks<2, 4>, k_pauli_chunks<2, 8>}};
+    used = kMaxBlocks;
+    hipLaunchKernelGGL(chunks[mode][ti], dim3(used), dim3(kThreads), 0, st, (const float4*)psi, a, scratch);
+  } else {
+    hipLaunchKernelGGL(table[nt_loads][mode][ti], dim3(blocks), dim3(kThreads), 0, st, (const float4*)psi, a,
+                       scratch);
+  }
   hipLaunchKernelGGL(k_column_sums<true>, dim3(1), dim3(64 * kFinalWaves), 0, st, (const double*)scratch,
-                     (int)blocks, kTerms, mode, a.odd, out);
+                     (int)used, kTerms, mode, a.odd, out);
   SV_HIP(hipGetLastError());
 }
 

@@ -49,7 +49,6 @@ __global__ __launch_bounds__(256) void k_phase(float4* __restrict__ psi, const u
   __shared__ double s_rho[kPhaseMaxQ];  // sum over the block's set bits b >= 10 of beta[q][b]
   __shared__ double s_theta_p;          // c + the polynomial on the block's bits alone
   const double* coef = reinterpret_cast<const double*>(data);
-  const int n = a.n;
   for (int i = threadIdx.x; i < kPhaseMaxQ * kPhaseMaxQ; i += 256) s_beta[i] = coef[1 + kPhaseMaxQ + i];
   if (threadIdx.x < kPhaseMaxQ) s_alpha[threadIdx.x] = coef[1 + threadIdx.x];
   __syncthreads();

@@ -78,6 +78,23 @@ def test_pauli_long_walks_at_23_qubits(flip):
         st.free()
 
 
+@pytest.mark.parametrize("flip", [0, 1, (1 << 26) | (1 << 2) | 1])
+def test_pauli_chunk_walk_at_27_qubits(flip):
+    """From 26 qubits up the sums walk the state in 32 KiB chunks per wave
+    (two rounds of chunks at 27 qubits for every item kind): three terms
+    per flip mask with z bits in the lane, step, wave and round fields and on
+    bit 0, against the oracle on the same random state."""
+    n = 27
+    st, psi = load_state(n, 41)
+    try:
+        zs = [(1 << 25) | (1 << 3) | 1, (1 << 13) | (1 << 9), (1 << 26) | (1 << 20) | (1 << 6) | (1 << 1)]
+        got = st.expect_pauli([flip] * 3, zs)
+        ref = np.array([oracle.pauli_expectation(psi, n, flip, z).real for z in zs])
+        assert np.max(np.abs(got - ref)) < 1e-12, (got, ref)
+    finally:
+        st.free()
+
+
 def test_pauli_ghz_closed_forms_at_30_qubits():
     from paper_2602_09604_amd import sv
     n = 30

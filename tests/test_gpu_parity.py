@@ -257,6 +257,26 @@ def test_norm_many_blocks_against_oracle(n):
         st.free()
 
 
+def test_basis_on_streamed_state():
+    """|index> on a 27-qubit state (the chunk-walk initialisation): the one
+    amplitude set, odd and even indices, its neighbours zero, norm 1."""
+    sv = _sv()
+    n = 27
+    st = sv.State(n)
+    try:
+        for index in ((1 << n) - 3, (1 << 26) + 2, 0, 12345):
+            st.set_basis(index)
+            lo = min(max(0, index - 4), (1 << n) - 8)
+            got = st.read(lo, 8)
+            want = np.zeros(8, dtype=np.complex64)
+            want[index - lo] = 1.0
+            assert np.array_equal(got, want), (index, got)
+            assert st.norm() == 1.0
+            assert np.count_nonzero(st.read((1 << n) - 4096, 4096)) == (1 if index >= (1 << n) - 4096 else 0)
+    finally:
+        st.free()
+
+
 def test_fp16x3_range_guard():
     """FP16X3 scales amplitudes by 2^14: a state whose sum |c|^2 may exceed
     15, or a gate that is not unitary, is rejected before any pass runs."""
